@@ -1,0 +1,188 @@
+/*
+ * aesgpu.h -- C ABI of libaesgpu: AES-128/192/256 ECB on AMD MI355X (gfx950).
+ *
+ * The operations follow Wang & Chu, "GPU Accelerated AES Algorithm"
+ * (arXiv:1902.05234): ECB mode (section 3.1.1, eq 1) over whole 16-byte
+ * blocks, one AES state per GPU thread (section 4.1), T-table rounds
+ * (section 3.2.3, eqs 22-26), round keys from one cipher key (section 3.2.2,
+ * Algorithm 1).  Where the paper is silent (key-expansion recurrence,
+ * decryption tables, byte order) the library follows FIPS-197.
+ *
+ * Conventions
+ *   - Every function returns an int status (AES_OK or a negative AES_E* code)
+ *     and never aborts; aes_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - "device pointer" = memory of the current HIP device (hipMalloc, or a
+ *     torch tensor's data_ptr()); "host pointer" = ordinary process memory.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *     work is enqueued asynchronously on it; the call returns without waiting.
+ *   - The caller owns every buffer.  No entry point allocates or frees device
+ *     memory; the library's only state is its immutable tables (in the code
+ *     object) and the tuning table set by aes_tune_set.
+ *   - A 16-byte block is processed byte-for-byte as FIPS-197's input array:
+ *     byte r + 4c is state row r, column c.  No padding is applied: callers
+ *     pass whole blocks.
+ */
+#ifndef AESGPU_H
+#define AESGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AES_OK 0
+#define AES_EINVAL (-1) /* bad argument: key size, Nr, null pointer, overlap */
+#define AES_EALIGN (-2) /* buffer not 16-byte aligned */
+#define AES_ENOMEM (-3) /* reserved: the library allocates nothing */
+#define AES_EHIP (-4)   /* HIP runtime or launch error */
+#define AES_EBUSY (-5)  /* reserved for callers' admission control */
+#define AES_ERANGE (-6) /* a count or capacity out of range */
+
+#define AES_MAX_ROUND_KEY_WORDS 60 /* 4 * (14 + 1) */
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *aes_last_error(void);
+
+/*
+ * aes_expand_key -- key schedule (section 3.2.2; Algorithm 1 keyExpansion).
+ *   key:     host pointer to keybits/8 bytes.
+ *   keybits: 128, 192 or 256.
+ *   rk_enc:  host array of >= 4*(Nr+1) uint32 (may be NULL): the expanded key;
+ *            round key k is words 4k..4k+3 (Nb = 4 words per round key, so
+ *            4*(10+1) words = 1408 bits for AES-128).  Word i holds key bytes
+ *            4i..4i+3 little-endian (byte 4i in bits 0..7).
+ *   rk_dec:  host array of >= 4*(Nr+1) uint32 (may be NULL): the schedule of
+ *            the equivalent inverse cipher (FIPS-197 5.3.5): rk_dec round 0 =
+ *            rk_enc round Nr, round Nr = rk_enc round 0, rounds 1..Nr-1 =
+ *            InvMixColumns(rk_enc round Nr-r).
+ *   nr:      receives Nr = 10/12/14 (may be NULL).
+ * Host only, thread-safe.  AES_EINVAL for a bad keybits or NULL key.
+ */
+int aes_expand_key(const uint8_t *key, int keybits, uint32_t *rk_enc, uint32_t *rk_dec, int *nr);
+
+/*
+ * aes_ecb_encrypt / aes_ecb_decrypt -- ECB over nblocks whole blocks
+ * (section 3.1.1, eq 1: C_i = cipher(P_i), each block independently).
+ *   rk:      host pointer to the 4*(nr+1)-word schedule from aes_expand_key
+ *            (rk_enc for encryption, rk_dec for decryption).  Copied into the
+ *            launch, so it may be freed when the call returns.
+ *   nr:      10, 12 or 14.
+ *   in, out: device pointers, 16-byte aligned, nblocks*16 bytes each.
+ *            in == out (in place) is allowed; any other overlap is AES_EINVAL.
+ *   nblocks: number of 16-byte blocks; 0 is a no-op returning AES_OK.
+ * The kernel variant comes from the tuning table (aes_tune_set), default
+ * 16 bytes per thread, 1024-thread workgroups, four replicated LDS T-tables.
+ */
+int aes_ecb_encrypt(const uint32_t *rk, int nr, const void *in, void *out, size_t nblocks, void *stream);
+int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_t nblocks, void *stream);
+
+/* Kernel variant of the plain path (the autotuner's search space). */
+#define AES_PLACEMENT_TTABLE4 0 /* four T-tables, 32 replicas each, in LDS */
+typedef struct {
+    int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes) */
+    int32_t wg;        /* workgroup size: multiple of 64 in [64, 1024] */
+    int32_t placement; /* AES_PLACEMENT_* */
+    int32_t grid;      /* workgroups; 0 = one per compute unit (persistent) */
+} aes_variant;
+
+/* Same as aes_ecb_encrypt/decrypt (decrypt != 0 selects decryption) with an
+ * explicit variant.  AES_EINVAL for a variant outside the search space. */
+int aes_ecb_crypt_variant(const uint32_t *rk, int nr, int decrypt, const void *in, void *out, size_t nblocks,
+                          const aes_variant *variant, void *stream);
+
+/* Tuning table used by aes_ecb_encrypt/decrypt: one variant per (nr,
+ * direction, size bucket of nblocks).  Buckets: <=256 blocks (4 KiB),
+ * <=4096 (64 KiB), <=65536 (1 MiB), <=524288 (8 MiB), larger.
+ * aes_tune_set is process-wide and thread-safe; grid is ignored. */
+#define AES_SIZE_BUCKETS 5
+int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant *v);
+int aes_tune_get(int nr, int decrypt, size_t nblocks, aes_variant *v);
+int aes_size_bucket(size_t nblocks);
+
+/*
+ * Batched ECB: many independent messages, each with its own key, key size
+ * and direction, in one persistent launch (not in the paper; the same
+ * per-block cipher as aes_ecb_encrypt/decrypt).
+ *
+ * Key table: device array of key slots, AES_KEY_SLOT_WORDS uint32 each:
+ *   words [0, 60)   encryption schedule, [64, 124) decryption schedule,
+ *   word 124        Nr.  aes_key_slot() fills one slot image on the host.
+ */
+#define AES_KEY_SLOT_WORDS 128
+#define AES_KEY_SLOT_ENC 0
+#define AES_KEY_SLOT_DEC 64
+#define AES_KEY_SLOT_NR 124
+int aes_key_slot(const uint8_t *key, int keybits, uint32_t *slot);
+
+/* One message: blocks [in_block, in_block+nblocks) of the input arena go to
+ * blocks [out_block, ...) of the output arena (units of 16 bytes). */
+typedef struct {
+    uint64_t in_block;
+    uint64_t out_block;
+    uint64_t nblocks;
+    uint32_t key_slot;
+    uint32_t decrypt; /* 0 = encrypt, nonzero = decrypt */
+} aes_msg;
+
+/* One work item: a chunk of at most chunk_blocks blocks of one message. */
+typedef struct {
+    uint64_t in_block;
+    uint64_t out_block;
+    uint32_t nblocks;
+    uint32_t key_slot;
+} aes_work_item;
+
+/*
+ * aes_batch_plan -- host only.  Splits msgs[0..nmsgs) into work items of at
+ * most chunk_blocks blocks, all encryption items first, then all decryption
+ * items, in message order.  items: host array of cap entries.  *n_enc and
+ * *n_dec receive the item counts even when the capacity is too small
+ * (AES_ERANGE), so a caller can size the array.  Messages with nblocks == 0
+ * produce no items.
+ */
+int aes_batch_plan(const aes_msg *msgs, size_t nmsgs, uint32_t chunk_blocks, aes_work_item *items, size_t cap,
+                   size_t *n_enc, size_t *n_dec);
+
+typedef struct {
+    int32_t bpt;        /* 1, 2, 4 */
+    int32_t wg;         /* multiple of 64 in [64, 1024] */
+    int32_t grid;       /* 0 = one workgroup per compute unit */
+    int32_t enc_groups; /* workgroups starting on the encryption list; <0 = by item share */
+} aes_batch_config;
+
+/*
+ * aes_ecb_batch -- one persistent launch over a planned work list.
+ *   items_dev:     device copy of the planned items (n_enc + n_dec entries).
+ *   key_table_dev: device key table of n_slots slots.
+ *   in_base/out_base: device arenas of in_blocks / out_blocks blocks, 16-byte
+ *                  aligned; the same arena for both is allowed (in place).
+ *   counters_dev:  device array of 4 uint32, all zero before the first launch:
+ *                  [0],[1] claim counters, [2] finished workgroups (the last
+ *                  workgroup resets [0..2] to zero, so the launch can be
+ *                  replayed, e.g. from a captured HIP graph), [3] the number of
+ *                  items rejected by the in-kernel checks (slot out of range,
+ *                  blocks outside an arena); [3] is never reset by the kernel.
+ *   cfg:           may be NULL for defaults.
+ * Launches that share counters_dev must not overlap in time.
+ */
+int aes_ecb_batch(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, const uint32_t *key_table_dev,
+                  size_t n_slots, const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
+                  uint32_t *counters_dev, const aes_batch_config *cfg, void *stream);
+
+/* Host copies of the library's source tables (for inspection and tests):
+ * sbox/inv_sbox 256 bytes each; te0/td0 256 column words each (eqs 22 and
+ * its decryption counterpart; T_k = rotl(T_0, 8k)).  Any pointer may be NULL. */
+int aes_host_tables(uint8_t *sbox, uint8_t *inv_sbox, uint32_t *te0, uint32_t *td0);
+
+/* Plain device copy of nbytes (multiple of 16, 16-byte aligned); the memory
+ * reference kernel used to calibrate HBM traffic counters. */
+int aes_device_copy(const void *in, void *out, size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AESGPU_H */

@@ -1,0 +1,297 @@
+"""ctypes binding of libaesgpu (include/aesgpu.h), same names as the C ABI.
+
+Argument marshalling only: every cipher step runs in the HIP kernels of
+libaesgpu.so.  PyTorch supplies device memory (uint8 CUDA tensors) and
+streams.  There is no fallback: if the library is missing or fails to load,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(HERE, "libaesgpu.so")
+
+AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0, -1, -2, -3, -4, -5, -6
+AES_PLACEMENT_TTABLE4 = 0
+AES_KEY_SLOT_WORDS, AES_KEY_SLOT_ENC, AES_KEY_SLOT_DEC, AES_KEY_SLOT_NR = 128, 0, 64, 124
+AES_SIZE_BUCKETS = 5
+
+MSG_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u8"),
+                      ("key_slot", "<u4"), ("decrypt", "<u4")])
+ITEM_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u4"), ("key_slot", "<u4")])
+assert MSG_DTYPE.itemsize == 32 and ITEM_DTYPE.itemsize == 24
+
+
+class AesError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("aesgpu error %d: %s" % (code, message))
+        self.code = code
+
+
+class _Variant(ctypes.Structure):
+    _fields_ = [("bpt", ctypes.c_int32), ("wg", ctypes.c_int32), ("placement", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("bpt", ctypes.c_int32), ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("enc_groups", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class Variant:
+    bpt: int = 1
+    wg: int = 1024
+    placement: int = AES_PLACEMENT_TTABLE4
+    grid: int = 0
+
+    def _c(self) -> _Variant:
+        return _Variant(self.bpt, self.wg, self.placement, self.grid)
+
+
+_lib_obj = None
+_lib_lock = threading.Lock()
+
+_c_p = ctypes.c_void_p
+_c_sz = ctypes.c_size_t
+_c_i = ctypes.c_int
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def library_path() -> str:
+    return LIBRARY
+
+
+def _lib() -> ctypes.CDLL:
+    global _lib_obj
+    if _lib_obj is not None:
+        return _lib_obj
+    with _lib_lock:
+        if _lib_obj is None:
+            if not os.path.exists(LIBRARY):
+                raise RuntimeError("libaesgpu.so is not built (%s); run `python -m paper_1902_05234_amd.build`" % LIBRARY)
+            # torch ships its own libamdhip64.so.7; loading it first makes the
+            # library's libamdhip64.so.7 dependency resolve to that same
+            # runtime, so torch's streams and device pointers are valid here.
+            import torch  # noqa: F401
+            lib = ctypes.CDLL(LIBRARY)
+            sig = {
+                "aes_last_error": ([], ctypes.c_char_p),
+                "aes_expand_key": ([_u8p, _c_i, _u32p, _u32p, ctypes.POINTER(_c_i)], _c_i),
+                "aes_key_slot": ([_u8p, _c_i, _u32p], _c_i),
+                "aes_ecb_encrypt": ([_u32p, _c_i, _c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_ecb_decrypt": ([_u32p, _c_i, _c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_ecb_crypt_variant": ([_u32p, _c_i, _c_i, _c_p, _c_p, _c_sz, ctypes.POINTER(_Variant), _c_p], _c_i),
+                "aes_tune_set": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
+                "aes_tune_get": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
+                "aes_size_bucket": ([_c_sz], _c_i),
+                "aes_batch_plan": ([_c_p, _c_sz, ctypes.c_uint32, _c_p, _c_sz, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_sz)], _c_i),
+                "aes_ecb_batch": ([_c_p, _c_sz, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
+                                   ctypes.POINTER(_BatchConfig), _c_p], _c_i),
+                "aes_device_copy": ([_c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_host_tables": ([_u8p, _u8p, _u32p, _u32p], _c_i),
+            }
+            for name, (args, res) in sig.items():
+                f = getattr(lib, name)
+                f.argtypes = args
+                f.restype = res
+            _lib_obj = lib
+    return _lib_obj
+
+
+def exported_symbols():
+    """Names this binding expects the library to export."""
+    return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
+            "aes_ecb_crypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
+            "aes_ecb_batch", "aes_device_copy", "aes_host_tables"]
+
+
+def aes_last_error() -> str:
+    return _lib().aes_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != AES_OK:
+        raise AesError(rc, aes_last_error())
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _blocks_of(t, name: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    nbytes = t.numel() * t.element_size()
+    if nbytes % 16:
+        raise ValueError("%s must hold whole 16-byte blocks (%d bytes)" % (name, nbytes))
+    return nbytes // 16
+
+
+def _u32_array(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    if n is not None and a.size < n:
+        raise ValueError("round-key array too short")
+    return a
+
+
+# --------------------------------------------------------------- key schedule
+@dataclass(frozen=True)
+class KeySchedule:
+    rk_enc: np.ndarray
+    rk_dec: np.ndarray
+    nr: int
+    keybits: int
+
+
+def aes_expand_key(key: bytes, keybits: int | None = None) -> KeySchedule:
+    key = bytes(key)
+    keybits = 8 * len(key) if keybits is None else int(keybits)
+    if keybits != 8 * len(key):
+        raise ValueError("key is %d bytes, keybits=%d" % (len(key), keybits))
+    kb = (ctypes.c_uint8 * max(1, len(key))).from_buffer_copy(key or b"\0")
+    enc = np.zeros(60, dtype=np.uint32)
+    dec = np.zeros(60, dtype=np.uint32)
+    nr = ctypes.c_int(0)
+    _check(_lib().aes_expand_key(kb, keybits, enc.ctypes.data_as(_u32p), dec.ctypes.data_as(_u32p), ctypes.byref(nr)))
+    n = 4 * (nr.value + 1)
+    return KeySchedule(enc[:n].copy(), dec[:n].copy(), nr.value, keybits)
+
+
+def aes_key_slot(key: bytes) -> np.ndarray:
+    key = bytes(key)
+    kb = (ctypes.c_uint8 * max(1, len(key))).from_buffer_copy(key or b"\0")
+    out = np.zeros(AES_KEY_SLOT_WORDS, dtype=np.uint32)
+    _check(_lib().aes_key_slot(kb, 8 * len(key), out.ctypes.data_as(_u32p)))
+    return out
+
+
+# ------------------------------------------------------------------ plain ECB
+def _crypt(fn, rk, nr, inp, out, nblocks, stream):
+    n_in = _blocks_of(inp, "in")
+    n_out = _blocks_of(out, "out")
+    nblocks = n_in if nblocks is None else int(nblocks)
+    if nblocks > n_in or nblocks > n_out:
+        raise ValueError("nblocks=%d exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
+    rk = _u32_array(rk, 4 * (int(nr) + 1))
+    _check(fn(rk.ctypes.data_as(_u32p), int(nr), inp.data_ptr(), out.data_ptr(), nblocks, _stream_handle(stream)))
+    return out
+
+
+def aes_ecb_encrypt(rk, nr: int, inp, out, nblocks: int | None = None, stream=None):
+    return _crypt(_lib().aes_ecb_encrypt, rk, nr, inp, out, nblocks, stream)
+
+
+def aes_ecb_decrypt(rk, nr: int, inp, out, nblocks: int | None = None, stream=None):
+    return _crypt(_lib().aes_ecb_decrypt, rk, nr, inp, out, nblocks, stream)
+
+
+def aes_ecb_crypt_variant(rk, nr: int, decrypt: bool, inp, out, variant: Variant, nblocks: int | None = None, stream=None):
+    lib = _lib()
+    v = variant._c()
+
+    def fn(rkp, nr_, i, o, n, s):
+        return lib.aes_ecb_crypt_variant(rkp, nr_, int(bool(decrypt)), i, o, n, ctypes.byref(v), s)
+
+    return _crypt(fn, rk, nr, inp, out, nblocks, stream)
+
+
+def aes_tune_set(nr: int, decrypt: bool, nblocks: int, variant: Variant):
+    v = variant._c()
+    _check(_lib().aes_tune_set(int(nr), int(bool(decrypt)), int(nblocks), ctypes.byref(v)))
+
+
+def aes_tune_get(nr: int, decrypt: bool, nblocks: int) -> Variant:
+    v = _Variant()
+    _check(_lib().aes_tune_get(int(nr), int(bool(decrypt)), int(nblocks), ctypes.byref(v)))
+    return Variant(v.bpt, v.wg, v.placement, v.grid)
+
+
+def aes_size_bucket(nblocks: int) -> int:
+    return int(_lib().aes_size_bucket(int(nblocks)))
+
+
+def ecb_encrypt(ks: KeySchedule, x, out=None, stream=None):
+    """Encrypt a uint8 CUDA tensor of whole blocks; returns ``out``."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    return aes_ecb_encrypt(ks.rk_enc, ks.nr, x, out, stream=stream)
+
+
+def ecb_decrypt(ks: KeySchedule, x, out=None, stream=None):
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    return aes_ecb_decrypt(ks.rk_dec, ks.nr, x, out, stream=stream)
+
+
+# ---------------------------------------------------------------- batched ECB
+def aes_batch_plan(msgs: np.ndarray, chunk_blocks: int):
+    """Host planner: returns (items [ITEM_DTYPE], n_enc, n_dec)."""
+    msgs = np.ascontiguousarray(msgs, dtype=MSG_DTYPE)
+    lib = _lib()
+    ne, nd = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    rc = lib.aes_batch_plan(msgs.ctypes.data if msgs.size else None, msgs.size, int(chunk_blocks), None, 0,
+                            ctypes.byref(ne), ctypes.byref(nd))
+    if rc not in (AES_OK, AES_ERANGE):
+        _check(rc)
+    n = ne.value + nd.value
+    items = np.zeros(n, dtype=ITEM_DTYPE)
+    if n:
+        _check(lib.aes_batch_plan(msgs.ctypes.data, msgs.size, int(chunk_blocks), items.ctypes.data, n,
+                                  ctypes.byref(ne), ctypes.byref(nd)))
+    return items, ne.value, nd.value
+
+
+@dataclass(frozen=True)
+class BatchConfig:
+    bpt: int = 1
+    wg: int = 1024
+    grid: int = 0
+    enc_groups: int = -1
+
+
+def aes_ecb_batch(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out_base, counters_dev,
+                  cfg: BatchConfig | None = None, stream=None):
+    """One persistent launch over a device work list (tensors: uint8/int views of device memory)."""
+    n_slots = (key_table_dev.numel() * key_table_dev.element_size()) // (4 * AES_KEY_SLOT_WORDS)
+    if items_dev.numel() * items_dev.element_size() < (n_enc + n_dec) * ITEM_DTYPE.itemsize:
+        raise ValueError("work list tensor smaller than n_enc + n_dec items")
+    if counters_dev.numel() * counters_dev.element_size() < 16:
+        raise ValueError("counters need 4 uint32")
+    c = cfg or BatchConfig()
+    bc = _BatchConfig(c.bpt, c.wg, c.grid, c.enc_groups)
+    _check(_lib().aes_ecb_batch(items_dev.data_ptr(), int(n_enc), int(n_dec), key_table_dev.data_ptr(), n_slots,
+                                in_base.data_ptr(), _blocks_of(in_base, "in_base"), out_base.data_ptr(),
+                                _blocks_of(out_base, "out_base"), counters_dev.data_ptr(), ctypes.byref(bc),
+                                _stream_handle(stream)))
+
+
+def aes_device_copy(inp, out, nbytes: int | None = None, stream=None):
+    nbytes = inp.numel() * inp.element_size() if nbytes is None else int(nbytes)
+    _check(_lib().aes_device_copy(inp.data_ptr(), out.data_ptr(), nbytes, _stream_handle(stream)))
+
+
+def aes_host_tables():
+    """(sbox, inv_sbox, te0, td0) as numpy arrays, from the library's host copy."""
+    sbox = np.zeros(256, dtype=np.uint8)
+    inv = np.zeros(256, dtype=np.uint8)
+    te0 = np.zeros(256, dtype=np.uint32)
+    td0 = np.zeros(256, dtype=np.uint32)
+    _check(_lib().aes_host_tables(sbox.ctypes.data_as(_u8p), inv.ctypes.data_as(_u8p), te0.ctypes.data_as(_u32p),
+                                  td0.ctypes.data_as(_u32p)))
+    return sbox, inv, te0, td0

@@ -1,0 +1,405 @@
+// aes_abi.cpp -- the extern "C" boundary of libaesgpu (declared in include/aesgpu.h).
+//
+// Host side only: argument checks, the key schedule, the batch planner and
+// the launch of the kernels in aes_ecb.hip / aes_batch.hip.  No entry point
+// allocates device memory, and none aborts: every failure is a status code
+// with a message available from aes_last_error().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/aesgpu.h"
+#include "aes_internal.hpp"
+#include "aes_tables.hpp"
+
+namespace aesgpu {
+namespace {
+
+constexpr TableSet kHostTables = make_tables();
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* what)
+{
+    return fail(AES_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int rounds_for_bits(int keybits)
+{
+    switch (keybits) {
+    case 128: return 10;
+    case 192: return 12;
+    case 256: return 14;
+    default: return -1;
+    }
+}
+
+bool valid_nr(int nr) { return nr == 10 || nr == 12 || nr == 14; }
+
+uint32_t sub_word(uint32_t x)
+{
+    return uint32_t(kHostTables.sbox[x & 0xff]) | (uint32_t(kHostTables.sbox[(x >> 8) & 0xff]) << 8) |
+           (uint32_t(kHostTables.sbox[(x >> 16) & 0xff]) << 16) | (uint32_t(kHostTables.sbox[x >> 24]) << 24);
+}
+
+// InvMixColumns of one column word: Td0[S[x]] is column 0 of the inverse
+// matrix times x, and column r is that word rotated by 8r bits.
+uint32_t inv_mix_column(uint32_t x)
+{
+    uint32_t r = 0;
+    for (int t = 0; t < 4; ++t)
+        r ^= rotl32(kHostTables.td0[kHostTables.sbox[(x >> (8 * t)) & 0xff]], 8 * t);
+    return r;
+}
+
+// Size buckets of the tuning table (blocks): <=4 KiB, <=64 KiB, <=1 MiB, <=8 MiB, larger.
+int size_bucket(uint64_t nblocks)
+{
+    if (nblocks <= 256) return 0;
+    if (nblocks <= 4096) return 1;
+    if (nblocks <= 65536) return 2;
+    if (nblocks <= 524288) return 3;
+    return 4;
+}
+
+struct TuneEntry {
+    std::atomic<int> bpt{1}, wg{1024}, placement{AES_PLACEMENT_TTABLE4};
+};
+TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
+
+int nr_index(int nr) { return (nr - 10) / 2; }
+
+std::atomic<int> g_cu_count[64];
+
+bool ranges_partially_overlap(const void* a, const void* b, uint64_t bytes)
+{
+    uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    if (x == y)
+        return false;
+    return x < y + bytes && y < x + bytes;
+}
+
+int check_buffers(const void* in, void* out, size_t nblocks)
+{
+    if (in == nullptr || out == nullptr)
+        return fail(AES_EINVAL, "null buffer pointer with nblocks=%zu", nblocks);
+    if (nblocks > (SIZE_MAX >> 5))
+        return fail(AES_EINVAL, "nblocks=%zu too large", nblocks);
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u)
+        return fail(AES_EALIGN, "in/out must be 16-byte aligned");
+    if (ranges_partially_overlap(in, out, (uint64_t)nblocks * 16u))
+        return fail(AES_EINVAL, "in and out overlap without being the same buffer");
+    return AES_OK;
+}
+
+int check_variant(const aes_variant* v)
+{
+    if (v->bpt != 1 && v->bpt != 2 && v->bpt != 4)
+        return fail(AES_EINVAL, "bpt must be 1, 2 or 4 (16, 32 or 64 bytes per thread), got %d", v->bpt);
+    if (v->wg < 64 || v->wg > 1024 || (v->wg % 64) != 0)
+        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", v->wg);
+    if (v->placement != AES_PLACEMENT_TTABLE4)
+        return fail(AES_EINVAL, "placement %d is not built in this library", v->placement);
+    if (v->grid < 0)
+        return fail(AES_EINVAL, "grid must be >= 0 (0 = persistent default), got %d", v->grid);
+    return AES_OK;
+}
+
+int run_ecb(const uint32_t* rk, int nr, bool decrypt, const void* in, void* out, size_t nblocks,
+            const aes_variant* v, void* stream)
+{
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (rk == nullptr)
+        return fail(AES_EINVAL, "null round-key pointer");
+    if (nblocks == 0)
+        return AES_OK;
+    int rc = check_buffers(in, out, nblocks);
+    if (rc != AES_OK)
+        return rc;
+    rc = check_variant(v);
+    if (rc != AES_OK)
+        return rc;
+    RoundKeys keys{};
+    std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    const uint64_t per_group = (uint64_t)v->wg * (uint64_t)v->bpt;
+    const uint64_t needed = (nblocks + per_group - 1) / per_group;
+    // one workgroup per CU: the replicated tables use 128-160 KiB of LDS
+    uint64_t grid = v->grid > 0 ? (uint64_t)v->grid : (uint64_t)cus;
+    grid = std::min<uint64_t>(grid, needed);
+    LaunchShape shape{v->bpt, v->wg, (int)grid};
+    hipError_t e = launch_ecb(shape, nr, decrypt, in, out, nblocks, keys, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "ECB kernel launch");
+    return AES_OK;
+}
+
+}  // namespace
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return -1;
+    int v = g_cu_count[dev].load(std::memory_order_relaxed);
+    if (v > 0)
+        return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        return -1;
+    g_cu_count[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
+}  // namespace aesgpu
+
+using namespace aesgpu;
+
+static_assert(sizeof(aes_work_item) == sizeof(WorkItem), "work item layout");
+static_assert(offsetof(aes_work_item, nblocks) == offsetof(WorkItem, nblocks), "work item layout");
+static_assert(offsetof(aes_work_item, key_slot) == offsetof(WorkItem, key_slot), "work item layout");
+
+extern "C" {
+
+const char* aes_last_error(void) { return g_err; }
+
+int aes_expand_key(const uint8_t* key, int keybits, uint32_t* rk_enc, uint32_t* rk_dec, int* nr_out)
+{
+    const int nr = rounds_for_bits(keybits);
+    if (nr < 0)
+        return fail(AES_EINVAL, "keybits must be 128, 192 or 256, got %d", keybits);
+    if (key == nullptr)
+        return fail(AES_EINVAL, "null key pointer");
+    const int nk = keybits / 32, total = 4 * (nr + 1);
+    uint32_t w[AES_MAX_ROUND_KEY_WORDS];
+    for (int i = 0; i < nk; ++i)
+        w[i] = uint32_t(key[4 * i]) | (uint32_t(key[4 * i + 1]) << 8) | (uint32_t(key[4 * i + 2]) << 16) |
+               (uint32_t(key[4 * i + 3]) << 24);
+    uint32_t rcon = 1;
+    for (int i = nk; i < total; ++i) {
+        uint32_t t = w[i - 1];
+        if (i % nk == 0) {
+            t = sub_word((t >> 8) | (t << 24)) ^ rcon;  // RotWord on a little-endian word is a right rotation
+            rcon = ((rcon << 1) ^ ((rcon & 0x80) ? 0x1b : 0)) & 0xff;
+        } else if (nk == 8 && i % nk == 4) {
+            t = sub_word(t);
+        }
+        w[i] = w[i - nk] ^ t;
+    }
+    if (rk_enc)
+        std::memcpy(rk_enc, w, sizeof(uint32_t) * total);
+    if (rk_dec) {
+        // equivalent inverse cipher: round order reversed, InvMixColumns on rounds 1..Nr-1
+        for (int j = 0; j < 4; ++j) {
+            rk_dec[j] = w[4 * nr + j];
+            rk_dec[4 * nr + j] = w[j];
+        }
+        for (int r = 1; r < nr; ++r)
+            for (int j = 0; j < 4; ++j)
+                rk_dec[4 * r + j] = inv_mix_column(w[4 * (nr - r) + j]);
+    }
+    if (nr_out)
+        *nr_out = nr;
+    return AES_OK;
+}
+
+int aes_key_slot(const uint8_t* key, int keybits, uint32_t* slot)
+{
+    if (slot == nullptr)
+        return fail(AES_EINVAL, "null slot pointer");
+    std::memset(slot, 0, sizeof(uint32_t) * AES_KEY_SLOT_WORDS);
+    int nr = 0;
+    int rc = aes_expand_key(key, keybits, slot + AES_KEY_SLOT_ENC, slot + AES_KEY_SLOT_DEC, &nr);
+    if (rc != AES_OK)
+        return rc;
+    slot[AES_KEY_SLOT_NR] = (uint32_t)nr;
+    return AES_OK;
+}
+
+int aes_ecb_encrypt(const uint32_t* rk, int nr, const void* in, void* out, size_t nblocks, void* stream)
+{
+    aes_variant v;
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    aes_tune_get(nr, 0, nblocks, &v);
+    return run_ecb(rk, nr, false, in, out, nblocks, &v, stream);
+}
+
+int aes_ecb_decrypt(const uint32_t* rk, int nr, const void* in, void* out, size_t nblocks, void* stream)
+{
+    aes_variant v;
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    aes_tune_get(nr, 1, nblocks, &v);
+    return run_ecb(rk, nr, true, in, out, nblocks, &v, stream);
+}
+
+int aes_ecb_crypt_variant(const uint32_t* rk, int nr, int decrypt, const void* in, void* out, size_t nblocks,
+                          const aes_variant* variant, void* stream)
+{
+    if (variant == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    return run_ecb(rk, nr, decrypt != 0, in, out, nblocks, variant, stream);
+}
+
+int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant* v)
+{
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (v == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    int rc = check_variant(v);
+    if (rc != AES_OK)
+        return rc;
+    TuneEntry& t = g_tune[nr_index(nr)][decrypt ? 1 : 0][size_bucket(nblocks)];
+    t.bpt.store(v->bpt);
+    t.wg.store(v->wg);
+    t.placement.store(v->placement);
+    return AES_OK;
+}
+
+int aes_tune_get(int nr, int decrypt, size_t nblocks, aes_variant* v)
+{
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (v == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    const TuneEntry& t = g_tune[nr_index(nr)][decrypt ? 1 : 0][size_bucket(nblocks)];
+    v->bpt = t.bpt.load();
+    v->wg = t.wg.load();
+    v->placement = t.placement.load();
+    v->grid = 0;
+    return AES_OK;
+}
+
+int aes_size_bucket(size_t nblocks) { return size_bucket(nblocks); }
+
+int aes_batch_plan(const aes_msg* msgs, size_t nmsgs, uint32_t chunk_blocks, aes_work_item* items, size_t cap,
+                   size_t* n_enc, size_t* n_dec)
+{
+    if (n_enc == nullptr || n_dec == nullptr)
+        return fail(AES_EINVAL, "null count pointer");
+    *n_enc = *n_dec = 0;
+    if (nmsgs > 0 && msgs == nullptr)
+        return fail(AES_EINVAL, "null message array with nmsgs=%zu", nmsgs);
+    if (chunk_blocks == 0)
+        return fail(AES_EINVAL, "chunk_blocks must be positive");
+    size_t ne = 0, nd = 0;
+    for (size_t i = 0; i < nmsgs; ++i) {
+        const uint64_t n = msgs[i].nblocks;
+        const uint64_t c = (n + chunk_blocks - 1) / chunk_blocks;
+        (msgs[i].decrypt ? nd : ne) += c;
+    }
+    *n_enc = ne;
+    *n_dec = nd;
+    if (ne + nd > UINT32_MAX)
+        return fail(AES_ERANGE, "too many work items (%zu)", ne + nd);
+    if (ne + nd > cap || (ne + nd > 0 && items == nullptr))
+        return fail(AES_ERANGE, "work list needs %zu items, capacity is %zu", ne + nd, cap);
+    size_t ie = 0, id = ne;
+    for (size_t i = 0; i < nmsgs; ++i) {
+        const aes_msg& m = msgs[i];
+        for (uint64_t off = 0; off < m.nblocks; off += chunk_blocks) {
+            aes_work_item& it = items[m.decrypt ? id++ : ie++];
+            it.in_block = m.in_block + off;
+            it.out_block = m.out_block + off;
+            it.nblocks = (uint32_t)std::min<uint64_t>(chunk_blocks, m.nblocks - off);
+            it.key_slot = m.key_slot;
+        }
+    }
+    return AES_OK;
+}
+
+int aes_ecb_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, const uint32_t* key_table_dev,
+                  size_t n_slots, const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks,
+                  uint32_t* counters_dev, const aes_batch_config* cfg, void* stream)
+{
+    if (n_enc + n_dec == 0)
+        return AES_OK;
+    if (n_enc + n_dec > UINT32_MAX || n_slots > UINT32_MAX)
+        return fail(AES_ERANGE, "work list or key table too large");
+    if (items_dev == nullptr || key_table_dev == nullptr || counters_dev == nullptr || in_base == nullptr ||
+        out_base == nullptr)
+        return fail(AES_EINVAL, "null pointer argument");
+    if ((reinterpret_cast<uintptr_t>(in_base) | reinterpret_cast<uintptr_t>(out_base)) & 15u)
+        return fail(AES_EALIGN, "in/out arenas must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(items_dev) & 7u) || (reinterpret_cast<uintptr_t>(key_table_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(counters_dev) & 3u))
+        return fail(AES_EALIGN, "work list / key table / counters misaligned");
+    if (ranges_partially_overlap(in_base, out_base, (uint64_t)std::min(in_blocks, out_blocks) * 16u))
+        return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
+    aes_batch_config c{1, 1024, 0, -1};
+    if (cfg)
+        c = *cfg;
+    if (c.bpt != 1 && c.bpt != 2 && c.bpt != 4)
+        return fail(AES_EINVAL, "bpt must be 1, 2 or 4, got %d", c.bpt);
+    if (c.wg < 64 || c.wg > 1024 || c.wg % 64)
+        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", c.wg);
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    int grid = c.grid > 0 ? c.grid : cus;
+    int enc_groups = c.enc_groups;
+    if (enc_groups < 0 || enc_groups > grid)
+        enc_groups = (int)((uint64_t)grid * n_enc / (n_enc + n_dec));
+    if (n_enc > 0 && enc_groups == 0)
+        enc_groups = 1;
+    if (n_dec > 0 && enc_groups == grid && grid > 1)
+        enc_groups = grid - 1;
+    BatchArgs a{reinterpret_cast<const WorkItem*>(items_dev), (uint32_t)n_enc, (uint32_t)n_dec, key_table_dev,
+                (uint32_t)n_slots, in_base, out_base, (uint64_t)in_blocks, (uint64_t)out_blocks, counters_dev,
+                (uint32_t)enc_groups};
+    hipError_t e = launch_batch(a, c.bpt, grid, c.wg, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "batch kernel launch");
+    return AES_OK;
+}
+
+int aes_host_tables(uint8_t* sbox, uint8_t* inv_sbox, uint32_t* te0, uint32_t* td0)
+{
+    if (sbox)
+        std::memcpy(sbox, kHostTables.sbox, 256);
+    if (inv_sbox)
+        std::memcpy(inv_sbox, kHostTables.inv_sbox, 256);
+    if (te0)
+        std::memcpy(te0, kHostTables.te0, sizeof(kHostTables.te0));
+    if (td0)
+        std::memcpy(td0, kHostTables.td0, sizeof(kHostTables.td0));
+    return AES_OK;
+}
+
+int aes_device_copy(const void* in, void* out, size_t nbytes, void* stream)
+{
+    if (nbytes == 0)
+        return AES_OK;
+    if (in == nullptr || out == nullptr)
+        return fail(AES_EINVAL, "null buffer pointer");
+    if (nbytes % 16 || ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u))
+        return fail(AES_EALIGN, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    hipError_t e = launch_copy(in, out, nbytes / 16, cus * 4, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "copy kernel launch");
+    return AES_OK;
+}
+
+}  // extern "C"

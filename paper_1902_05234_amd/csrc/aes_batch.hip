@@ -1,0 +1,153 @@
+// aes_batch.hip -- one persistent launch over many independent ECB messages.
+//
+// The host splits every message into work items of at most `chunk` blocks
+// (aes_batch_plan) and lists all encryption items before all decryption
+// items.  Each wave claims one item at a time with an atomic counter, loads
+// that item's round keys as uniform values, and runs the same round core as
+// the plain kernel for the item's key size.
+//
+// LDS holds the tables of one direction only (128 KiB + 32 KiB), so the
+// workgroups are split by role: the first `enc_groups` start on the
+// encryption list, the others on the decryption list; when a list runs dry a
+// workgroup reloads LDS with the other direction's tables and helps drain the
+// other list.  The last workgroup to finish resets the claim counters, so a
+// captured graph can replay the launch with no separate reset node.
+//
+// Every item is checked against the arena sizes and the key-table size
+// before use; a bad item is skipped and counted in counters[3].
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "aes_device.hpp"
+#include "aes_internal.hpp"
+
+namespace aesgpu {
+
+constexpr int kSlotWords = 128;  // rk_enc at 0, rk_dec at 64, Nr at 124
+constexpr int kSlotNr = 124;
+
+template <int NR, bool kDecrypt, int BPT>
+__device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __restrict__ out, uint32_t nblocks,
+                                         const uint32_t* lds, const LaneBases& lb, const uint32_t* __restrict__ kp)
+{
+    uint32_t k[4 * (NR + 1)];
+#pragma unroll
+    for (int i = 0; i < 4 * (NR + 1); ++i)
+        k[i] = __builtin_amdgcn_readfirstlane(kp[i]);
+    auto key = [&](int i) { return k[i]; };
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += 64u * BPT) {
+        const uint32_t first = b0 + lane;
+        if (b0 + 64u * BPT <= nblocks) {
+            uint4 x[BPT];
+#pragma unroll
+            for (int j = 0; j < BPT; ++j)
+                x[j] = in[first + 64u * j];
+#pragma unroll
+            for (int j = 0; j < BPT; ++j)
+                x[j] = crypt_block<NR, kDecrypt>(x[j], lds, lb, key);
+#pragma unroll
+            for (int j = 0; j < BPT; ++j)
+                out[first + 64u * j] = x[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                uint32_t b = first + 64u * j;
+                if (b < nblocks)
+                    out[b] = crypt_block<NR, kDecrypt>(in[b], lds, lb, key);
+            }
+        }
+    }
+}
+
+template <bool kDecrypt, int BPT>
+__device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32_t first_item, uint32_t n_items,
+                                      const uint32_t* __restrict__ key_table, uint32_t n_slots,
+                                      const uint4* __restrict__ in_base, uint4* __restrict__ out_base,
+                                      uint64_t in_blocks, uint64_t out_blocks, uint32_t* counters,
+                                      const uint32_t* lds, const LaneBases& lb)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane == 0)
+            idx = atomicAdd(&counters[kDecrypt ? 1 : 0], 1u);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= n_items)
+            break;
+        const WorkItem it = items[first_item + idx];
+        const uint64_t in_b = __builtin_amdgcn_readfirstlane((uint32_t)it.in_block) |
+                              ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it.in_block >> 32)) << 32);
+        const uint64_t out_b = __builtin_amdgcn_readfirstlane((uint32_t)it.out_block) |
+                               ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it.out_block >> 32)) << 32);
+        const uint32_t nb = __builtin_amdgcn_readfirstlane(it.nblocks);
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(it.key_slot);
+        const bool ok = slot < n_slots && in_b <= in_blocks && nb <= in_blocks - in_b && out_b <= out_blocks &&
+                        nb <= out_blocks - out_b;
+        const uint32_t* kp = key_table + (uint64_t)slot * kSlotWords;
+        const int nr = ok ? (int)__builtin_amdgcn_readfirstlane(kp[kSlotNr]) : 0;
+        const uint32_t* kd = kp + (kDecrypt ? 64 : 0);
+        switch (nr) {
+        case 10: run_item<10, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        case 12: run_item<12, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        case 14: run_item<14, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        default:
+            if (lane == 0)
+                atomicAdd(&counters[3], 1u);
+            break;
+        }
+    }
+}
+
+template <int BPT>
+__global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict__ items, uint32_t n_enc,
+                                                     uint32_t n_dec, const uint32_t* __restrict__ key_table,
+                                                     uint32_t n_slots, const uint4* __restrict__ in_base,
+                                                     uint4* __restrict__ out_base, uint64_t in_blocks,
+                                                     uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups)
+{
+    __shared__ uint32_t lds[kDecLdsWords];
+    const LaneBases lb(threadIdx.x);
+    bool dec = blockIdx.x >= enc_groups;
+    for (int pass = 0; pass < 2; ++pass, dec = !dec) {
+        if (dec)
+            fill_tables<true>(lds, &c_tables);
+        else
+            fill_tables<false>(lds, &c_tables);
+        __syncthreads();
+        if (dec)
+            drain<true, BPT>(items, n_enc, n_dec, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
+                             counters, lds, lb);
+        else
+            drain<false, BPT>(items, 0, n_enc, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
+                              counters, lds, lb);
+        __syncthreads();  // every wave is done with these tables before LDS is refilled
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[2], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+            atomicExch(&counters[2], 0u);
+            __threadfence();
+        }
+    }
+}
+
+hipError_t launch_batch(const BatchArgs& a, int bpt, int grid, int wg, hipStream_t stream)
+{
+#define AESGPU_BATCH_LAUNCH(B)                                                                                  \
+    hipLaunchKernelGGL(batch_kernel<B>, dim3(grid), dim3(wg), 0, stream, a.items, a.n_enc, a.n_dec, a.key_table, \
+                       a.n_slots, static_cast<const uint4*>(a.in_base), static_cast<uint4*>(a.out_base),        \
+                       a.in_blocks, a.out_blocks, a.counters, a.enc_groups)
+    switch (bpt) {
+    case 1: AESGPU_BATCH_LAUNCH(1); break;
+    case 2: AESGPU_BATCH_LAUNCH(2); break;
+    case 4: AESGPU_BATCH_LAUNCH(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef AESGPU_BATCH_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace aesgpu

@@ -1,0 +1,52 @@
+// aes_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace aesgpu {
+
+// Round keys passed by value in the kernel argument block; the kernels read
+// them as uniform values (scalar registers).
+struct RoundKeys {
+    uint32_t w[60];
+};
+
+struct LaunchShape {
+    int bpt;   // blocks per thread per iteration: 1, 2, 4
+    int wg;    // workgroup size (multiple of 64, at most 1024)
+    int grid;  // number of workgroups
+};
+
+hipError_t launch_ecb(const LaunchShape& shape, int nr, bool decrypt, const void* in, void* out, uint64_t nblocks,
+                      const RoundKeys& rk, hipStream_t stream);
+
+hipError_t launch_copy(const void* in, void* out, uint64_t n16, int grid, hipStream_t stream);
+
+// Work item of the batched kernel: one wave-sized chunk of one message.
+struct WorkItem {
+    uint64_t in_block;
+    uint64_t out_block;
+    uint32_t nblocks;
+    uint32_t key_slot;
+};
+
+struct BatchArgs {
+    const WorkItem* items;
+    uint32_t n_enc;        // items [0, n_enc) encrypt
+    uint32_t n_dec;        // items [n_enc, n_enc + n_dec) decrypt
+    const uint32_t* key_table;
+    uint32_t n_slots;
+    const void* in_base;
+    void* out_base;
+    uint64_t in_blocks;    // arena sizes, for the per-item bounds check
+    uint64_t out_blocks;
+    uint32_t* counters;    // [0] next enc item, [1] next dec item, [2] finished groups, [3] rejected items
+    uint32_t enc_groups;   // workgroups that start on the encryption list
+};
+
+hipError_t launch_batch(const BatchArgs& args, int bpt, int grid, int wg, hipStream_t stream);
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+}  // namespace aesgpu

@@ -113,3 +113,12 @@ def mean_trace_bytes() -> float:
     def lu_mean(a, b):
         return (b - a) / np.log(b / a)
     return 0.8 * lu_mean(64, 16 << 10) + 0.2 * lu_mean(1 << 20, 64 << 20)
+
+
+def device_random_bytes(seed: int, nbytes: int, device="cuda"):
+    """``nbytes`` uniform random bytes generated on the GPU by torch's seeded
+    Philox generator (for buffers too large to draw on the host)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(np.random.SeedSequence([BASE_SEED, 6, seed]).generate_state(1)[0]))
+    return torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=device, generator=g)

@@ -1,0 +1,270 @@
+"""CPU tests of libaesgpu's host side: exported symbols, key schedules, the
+T-tables (checked against GF(2^8) products from the oracle), a numpy
+emulation of the kernels' round structure against the oracle, argument
+checking, tuning table and batch planner.  No GPU is touched."""
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from paper_1902_05234_amd import aes, inputs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "aesgpu.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aes_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    lib = aes._lib()
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(aes.exported_symbols())
+
+
+def le_words(b: bytes) -> np.ndarray:
+    return np.frombuffer(b, dtype="<u4").astype(np.uint32)
+
+
+@pytest.mark.parametrize("keybits", [128, 192, 256])
+def test_encryption_schedule_matches_oracle(oracle_lib, keybits):
+    for s in range(20):
+        key = inputs.random_key(500 + s, keybits)
+        ks = aes.aes_expand_key(key)
+        w, nr = oracle_lib.expand_key(key)
+        assert ks.nr == nr
+        assert np.array_equal(ks.rk_enc, le_words(w))
+
+
+@pytest.mark.parametrize("keybits", [128, 192, 256])
+def test_decryption_schedule_structure(oracle_lib, keybits):
+    key = inputs.random_key(77, keybits)
+    ks = aes.aes_expand_key(key)
+    nr = ks.nr
+    e = ks.rk_enc.reshape(nr + 1, 4)
+    d = ks.rk_dec.reshape(nr + 1, 4)
+    assert np.array_equal(d[0], e[nr]) and np.array_equal(d[nr], e[0])
+    for r in range(1, nr):
+        want = oracle_lib.inv_mix_columns(e[nr - r].astype("<u4").tobytes())
+        assert d[r].astype("<u4").tobytes() == want
+
+
+def test_key_slot_layout():
+    key = inputs.random_key(3, 192)
+    slot = aes.aes_key_slot(key)
+    ks = aes.aes_expand_key(key)
+    n = 4 * (ks.nr + 1)
+    assert np.array_equal(slot[:n], ks.rk_enc)
+    assert np.array_equal(slot[64:64 + n], ks.rk_dec)
+    assert slot[124] == ks.nr
+    assert not slot[n:64].any() and not slot[64 + n:124].any()
+
+
+def rotl(x, n):
+    x = np.asarray(x, dtype=np.uint64)
+    return (((x << n) | (x >> (32 - n))) & 0xFFFFFFFF).astype(np.uint32) if n else np.asarray(x, dtype=np.uint32)
+
+
+def test_t_tables_are_the_papers_gf_products(oracle_lib):
+    """Eqs 22-25: T_k column of entry w is the GF multiples of s = sbox(w)
+    given in tests/golden/paper_t_tables.txt; decryption tables use the
+    inverse MixColumns multipliers on InvS(w)."""
+    sbox, inv, te0, td0 = aes.aes_host_tables()
+    assert np.array_equal(sbox, oracle_lib.sbox())
+    assert np.array_equal(inv, oracle_lib.inv_sbox())
+    m = oracle_lib.gf_mul_table()
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_t_tables.txt")):
+        if line.strip() and not line.startswith("#"):
+            name, *mult = line.split()
+            rows[int(name[1])] = [int(v, 16) for v in mult]
+    s = oracle_lib.sbox()
+    for k in range(4):
+        tk = rotl(te0, 8 * k)
+        for r in range(4):
+            assert np.array_equal((tk >> (8 * r)) & 0xFF, m[rows[k][r], s]), (k, r)
+    ai = oracle_lib.inv_mix_matrix()
+    si = oracle_lib.inv_sbox()
+    for k in range(4):
+        tk = rotl(td0, 8 * k)
+        for r in range(4):
+            assert np.array_equal((tk >> (8 * r)) & 0xFF, m[ai[r, k], si]), (k, r)
+
+
+# ------------------------------------------------------- numpy kernel emulation
+def emulate(ks, data: np.ndarray, decrypt: bool) -> np.ndarray:
+    """The kernels' arithmetic on the CPU: eq 26 rounds with the library's
+    tables and schedules, final round from T-table bytes (enc) or InvS (dec)."""
+    sbox, inv, te0, td0 = aes.aes_host_tables()
+    T = [rotl(td0 if decrypt else te0, 8 * k).astype(np.uint32) for k in range(4)]
+    rk = (ks.rk_dec if decrypt else ks.rk_enc).astype(np.uint32)
+    w = data.reshape(-1, 4).copy().view(np.uint32) if data.dtype == np.uint32 else np.frombuffer(data.tobytes(), dtype="<u4").reshape(-1, 4).astype(np.uint32)
+    w = w ^ rk[0:4]
+    s = 3 if decrypt else 1
+    b = lambda x, t: ((x >> (8 * t)) & 0xFF).astype(np.intp)
+    for r in range(1, ks.nr):
+        e = np.empty_like(w)
+        for j in range(4):
+            e[:, j] = (T[0][b(w[:, j], 0)] ^ T[1][b(w[:, (j + s) % 4], 1)] ^ T[2][b(w[:, (j + 2 * s) % 4], 2)]
+                       ^ T[3][b(w[:, (j + 3 * s) % 4], 3)] ^ rk[4 * r + j])
+        w = e
+    out = np.empty_like(w)
+    box = inv if decrypt else sbox
+    for j in range(4):
+        v = np.zeros(w.shape[0], dtype=np.uint32)
+        for t in range(4):
+            v |= box[b(w[:, (j + t * s) % 4], t)].astype(np.uint32) << (8 * t)
+        out[:, j] = v ^ rk[4 * ks.nr + j]
+    return out.astype("<u4").view(np.uint8).reshape(-1)
+
+
+@pytest.mark.parametrize("keybits", [128, 192, 256])
+def test_table_emulation_matches_oracle(oracle_lib, keybits):
+    key = inputs.random_key(11, keybits)
+    ks = aes.aes_expand_key(key)
+    x = inputs.random_bytes(12, 16 * 4099)
+    c = emulate(ks, x, False)
+    assert np.array_equal(c, oracle_lib.ecb_encrypt(key, x))
+    p = emulate(ks, c, True)
+    assert np.array_equal(p, x)
+    assert np.array_equal(emulate(ks, x, True), oracle_lib.ecb_decrypt(key, x))
+
+
+def test_single_round_identity_eq26(oracle_lib):
+    """One T-table round equals SubBytes, ShiftRows, MixColumns, AddRoundKey
+    for all 16 x 256 single-byte states and random states."""
+    _, _, te0, _ = aes.aes_host_tables()
+    T = [rotl(te0, 8 * k) for k in range(4)]
+    g = inputs.rng(7)
+    states = [bytes(16)]
+    for pos in range(16):
+        for v in range(256):
+            blk = bytearray(16)
+            blk[pos] = v
+            states.append(bytes(blk))
+    states += [g.integers(0, 256, 16, dtype=np.uint8).tobytes() for _ in range(500)]
+    k = g.integers(0, 256, 16, dtype=np.uint8).tobytes()
+    kw = le_words(k)
+    for st_ in states:
+        want = oracle_lib.add_round_key(oracle_lib.mix_columns(oracle_lib.shift_rows(oracle_lib.sub_bytes(st_))), k)
+        w = le_words(st_)
+        e = [int(T[0][w[j] & 0xFF] ^ T[1][(w[(j + 1) % 4] >> 8) & 0xFF] ^ T[2][(w[(j + 2) % 4] >> 16) & 0xFF]
+                 ^ T[3][(w[(j + 3) % 4] >> 24) & 0xFF] ^ kw[j]) for j in range(4)]
+        assert np.array(e, dtype="<u4").tobytes() == want
+
+
+# ------------------------------------------------------------- error handling
+class FakePtr:
+    """Stands in for a tensor: only data_ptr/numel are used by the binding's checks."""
+
+
+def call_raw(fn_name, *args):
+    return getattr(aes._lib(), fn_name)(*args)
+
+
+def test_expand_key_rejects_bad_sizes():
+    lib = aes._lib()
+    rk = (aes.ctypes.c_uint32 * 60)()
+    key = (aes.ctypes.c_uint8 * 32)()
+    for bits in (0, 64, 127, 129, 160, 224, 512, -128):
+        assert lib.aes_expand_key(key, bits, rk, rk, None) == aes.AES_EINVAL
+        assert "keybits" in aes.aes_last_error()
+    assert lib.aes_expand_key(None, 128, rk, rk, None) == aes.AES_EINVAL
+    with pytest.raises(aes.AesError):
+        aes.aes_expand_key(b"\0" * 20)
+
+
+def test_ecb_argument_checks_before_any_device_call():
+    lib = aes._lib()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    A, B = 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+    assert lib.aes_ecb_encrypt(rk, 11, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_decrypt(rk, 9, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_encrypt(None, 10, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_encrypt(rk, 10, A, B, 0, None) == aes.AES_OK           # empty: no launch
+    assert lib.aes_ecb_encrypt(rk, 10, None, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_encrypt(rk, 10, A, None, 4, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_encrypt(rk, 10, A + 4, B, 4, None) == aes.AES_EALIGN
+    assert lib.aes_ecb_encrypt(rk, 10, A, B + 8, 4, None) == aes.AES_EALIGN
+    assert lib.aes_ecb_encrypt(rk, 10, A, A + 16, 4, None) == aes.AES_EINVAL  # partial overlap
+    assert "overlap" in aes.aes_last_error()
+    bad = [aes.Variant(bpt=3), aes.Variant(wg=100), aes.Variant(wg=2048), aes.Variant(placement=7), aes.Variant(grid=-1)]
+    for v in bad:
+        cv = v._c()
+        assert lib.aes_ecb_crypt_variant(rk, 10, 0, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
+    assert lib.aes_ecb_crypt_variant(rk, 10, 0, A, B, 4, None, None) == aes.AES_EINVAL
+
+
+def test_tuning_table_round_trip():
+    for nr in (10, 12, 14):
+        for dec in (False, True):
+            for nb in (1, 300, 5000, 70000, 1 << 22):
+                v = aes.Variant(bpt=2, wg=512)
+                aes.aes_tune_set(nr, dec, nb, v)
+                got = aes.aes_tune_get(nr, dec, nb)
+                assert (got.bpt, got.wg, got.placement) == (2, 512, aes.AES_PLACEMENT_TTABLE4)
+                aes.aes_tune_set(nr, dec, nb, aes.Variant())
+    assert [aes.aes_size_bucket(n) for n in (1, 256, 257, 4096, 4097, 65536, 65537, 524288, 524289)] == [0, 0, 1, 1, 2, 2, 3, 3, 4]
+    with pytest.raises(aes.AesError):
+        aes.aes_tune_set(10, False, 1, aes.Variant(bpt=8))
+    with pytest.raises(aes.AesError):
+        aes.aes_tune_get(13, False, 1)
+
+
+def test_batch_launch_checks():
+    lib = aes._lib()
+    cfg = aes._BatchConfig(1, 1024, 0, -1)
+    assert lib.aes_ecb_batch(None, 0, 0, None, 0, None, 0, None, 0, None, None, None) == aes.AES_OK
+    assert lib.aes_ecb_batch(None, 1, 0, 0x1000, 1, 0x2000, 1, 0x3000, 1, 0x4000, None, None) == aes.AES_EINVAL
+    assert lib.aes_ecb_batch(0x1000, 1, 0, 0x1000, 1, 0x2008, 1, 0x3000, 1, 0x4000, None, None) == aes.AES_EALIGN
+    cfg.bpt = 5
+    assert lib.aes_ecb_batch(0x1000, 1, 0, 0x1000, 1, 0x2000, 1, 0x3000, 1, 0x4000, aes.ctypes.byref(cfg), None) == aes.AES_EINVAL
+
+
+# --------------------------------------------------------------- batch planner
+def make_msgs(nblocks, decrypt, slots=None):
+    m = np.zeros(len(nblocks), dtype=aes.MSG_DTYPE)
+    m["nblocks"] = nblocks
+    off = np.concatenate([[0], np.cumsum(nblocks)[:-1]]) if len(nblocks) else []
+    m["in_block"] = off
+    m["out_block"] = np.asarray(off, dtype=np.uint64) + 7
+    m["decrypt"] = decrypt
+    m["key_slot"] = slots if slots is not None else np.arange(len(nblocks))
+    return m
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.tuples(st.integers(0, 5000), st.booleans()), max_size=40), st.integers(1, 2048))
+def test_batch_plan_covers_every_block_once(msgs, chunk):
+    m = make_msgs([n for n, _ in msgs], [int(d) for _, d in msgs])
+    items, ne, nd = aes.aes_batch_plan(m, chunk)
+    assert ne + nd == len(items)
+    assert (items["nblocks"] >= 1).all() and (items["nblocks"] <= chunk).all()
+    for i, msg in enumerate(m):
+        part = items[:ne] if not msg["decrypt"] else items[ne:]
+        mine = part[part["key_slot"] == i]
+        assert int(mine["nblocks"].sum()) == int(msg["nblocks"])
+        if len(mine):
+            assert mine["in_block"][0] == msg["in_block"]
+            assert (np.diff(mine["in_block"].astype(np.int64)) == chunk).all()
+            assert (mine["out_block"] - mine["in_block"] == 7).all()
+
+
+def test_batch_plan_capacity_and_errors():
+    lib = aes._lib()
+    m = make_msgs([100, 3], [0, 1])
+    ne, nd = aes.ctypes.c_size_t(), aes.ctypes.c_size_t()
+    items = np.zeros(1, dtype=aes.ITEM_DTYPE)
+    rc = lib.aes_batch_plan(m.ctypes.data, 2, 64, items.ctypes.data, 1, aes.ctypes.byref(ne), aes.ctypes.byref(nd))
+    assert rc == aes.AES_ERANGE and (ne.value, nd.value) == (2, 1)
+    assert lib.aes_batch_plan(m.ctypes.data, 2, 0, items.ctypes.data, 1, aes.ctypes.byref(ne), aes.ctypes.byref(nd)) == aes.AES_EINVAL
+    assert lib.aes_batch_plan(None, 2, 8, None, 0, aes.ctypes.byref(ne), aes.ctypes.byref(nd)) == aes.AES_EINVAL
+    items, ne_, nd_ = aes.aes_batch_plan(np.zeros(0, dtype=aes.MSG_DTYPE), 64)
+    assert len(items) == 0 and ne_ == nd_ == 0
