@@ -1,0 +1,352 @@
+#!/usr/bin/env python3
+"""Benchmark of the AES-ECB hot path on one MI355X.
+
+One step = expand the key (host), encrypt a 1 GiB device buffer with
+AES-128 ECB, decrypt the ciphertext again (two launches of the plain
+persistent kernels).  Inputs are seeded synthetic bytes resident in HBM
+before timing starts.  Prints ONE JSON line:
+
+  value        whole-step throughput, 10^9 payload bytes per second
+               (encrypt + decrypt bytes / wall time of the timed steps)
+  roofline     the encrypt kernel against the LDS lookup roof (the binding
+               unit: 16 table lookups per block per round), with the HBM and
+               VALU roofs beside it
+  cpu_baseline the CPU oracle (byte-wise FIPS-197, all host cores) on a
+               bounded slice of the same workload
+  batched      20,000 mixed messages in one persistent launch (graph replay)
+               vs per-message plain launches and vs the bulk-equivalent rate
+  sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB
+
+Flags: --gpus N (only 1 is supported), --steps K, --warmup W,
+--no-batch / --no-sweep / --no-cpu to skip sections, --profile to run only a
+few bulk and copy launches (for rocprofv3).
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import platform
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GiB = 1 << 30
+MiB = 1 << 20
+
+# MI355X published figures (gfx950): 256 CUs at 2.4 GHz peak engine clock.
+MI355X_CUS = 256
+MI355X_CLOCK_HZ = 2.4e9
+HBM_PEAK_BPS = 8.0e12
+LDS_LOOKUPS_PER_CLK_PER_CU = 32          # 32 banks x 4 B per clock, one ds_read_b32 lane each
+VALU_LANE_OPS_PER_CLK_PER_CU = 128       # fp32 vector peak 157.3 TFLOP/s = 2 x 78.6 T lane-ops/s
+LDS_PEAK = MI355X_CUS * MI355X_CLOCK_HZ * LDS_LOOKUPS_PER_CLK_PER_CU     # 19.66 T lookups/s
+VALU_PEAK = MI355X_CUS * MI355X_CLOCK_HZ * VALU_LANE_OPS_PER_CLK_PER_CU  # 78.6 T lane-ops/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lookups_per_block(nr: int) -> int:
+    return 16 * nr                      # 16 per inner round + 16 in the final round
+
+
+def valu_floor_per_block(nr: int) -> int:
+    return 24 * nr + 12                 # address/byte-select + XOR3 + final merge
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1902_05234_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(nbytes_payload: int):
+    """HBM bytes per encrypt launch from the committed rocprofv3 PMC summary,
+    or None if it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "aes128_ecb_encrypt_1GiB_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_hash:\s*(\w+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+class Timer:
+    """HIP events on the stream the kernels are launched on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def run(self, fn):
+        s = self.torch.cuda.current_stream()
+        a = self.torch.cuda.Event(enable_timing=True)
+        b = self.torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        self.pairs.append((a, b))
+
+    def ms(self):
+        self.torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+
+def bulk(torch, aes, inputs, args):
+    nbytes = GiB
+    key = inputs.random_key(1, 128)
+    x = inputs.device_random_bytes(1, nbytes)
+    c = torch.empty_like(x)
+    p = torch.empty_like(x)
+    t_enc, t_dec = Timer(torch), Timer(torch)
+
+    def step(timed: bool):
+        ks = aes.aes_expand_key(key)
+        if timed:
+            t_enc.run(lambda: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, c))
+            t_dec.run(lambda: aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, c, p))
+        else:
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, c)
+            aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, c, p)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if not torch.equal(p, x):
+        raise RuntimeError("round trip failed on the 1 GiB buffer")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    enc_ms, dec_ms = t_enc.ms(), t_dec.ms()
+    return dict(key=key, x=x, c=c, nbytes=nbytes, elapsed=elapsed, enc_ms=enc_ms, dec_ms=dec_ms)
+
+
+def roofline(b, traffic):
+    nblocks = b["nbytes"] // 16
+    t = sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3
+    nr = 10
+    lookups = lookups_per_block(nr) * nblocks
+    ach = lookups / t / 1e9
+    peak = LDS_PEAK / 1e9
+    hbm_alg = 32 * nblocks
+    return {
+        "kernel": "ecb_kernel<Nr=10, encrypt, 16 B/thread>",
+        "bound": "lds",
+        "achieved": round(ach, 1),
+        "peak": round(peak, 1),
+        "unit": "Glookup/s",
+        "frac": round(ach / peak, 4),
+        "traffic": traffic,
+        "per_launch": {"blocks": nblocks, "lookups": lookups, "hbm_bytes_algorithmic": hbm_alg,
+                       "avg_ms": round(t * 1e3, 4)},
+        "roofs": {
+            "lds": {"achieved_Glookup_s": round(ach, 1), "peak": round(peak, 1), "frac": round(ach / peak, 4)},
+            "hbm": {"achieved_GB_s": round(hbm_alg / t / 1e9, 1), "peak": HBM_PEAK_BPS / 1e9,
+                    "frac": round(hbm_alg / t / HBM_PEAK_BPS, 4)},
+            "valu_floor": {"achieved_Tlane_op_s": round(valu_floor_per_block(nr) * nblocks / t / 1e12, 2),
+                           "peak": round(VALU_PEAK / 1e12, 1),
+                           "frac": round(valu_floor_per_block(nr) * nblocks / t / VALU_PEAK, 4)},
+            "payload_roof_GB_s": round(min(LDS_PEAK * 16 / lookups_per_block(nr), HBM_PEAK_BPS / 2,
+                                           VALU_PEAK * 16 / valu_floor_per_block(nr)) / 1e9, 1),
+        },
+    }
+
+
+def cpu_baseline(b, args):
+    import numpy as np
+
+    import oracle
+    o = oracle.load()
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    probe = b["x"][:MiB].cpu().numpy()
+    t0 = time.perf_counter()
+    o.ecb_encrypt(b["key"], probe, nthreads=cores)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    nbytes = int(min(256 * MiB, max(MiB, args.cpu_seconds / 2 / dt * MiB)))
+    nbytes -= nbytes % MiB
+    xs = b["x"][:nbytes].cpu().numpy()
+    t0 = time.perf_counter()
+    enc = o.ecb_encrypt(b["key"], xs, nthreads=cores)
+    dec = o.ecb_decrypt(b["key"], enc, nthreads=cores)
+    dt = time.perf_counter() - t0
+    gpu_match = bool(np.array_equal(enc, b["c"][:nbytes].cpu().numpy())) and bool(np.array_equal(dec, xs))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(2 * nbytes / dt / 1e9, 6), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": "AES-128 ECB encrypt then decrypt of the first %d MiB of the 1 GiB workload" % (nbytes // MiB),
+            "seconds": round(dt, 2), "cpu_model": model or platform.processor(),
+            "matches_gpu_on_sample": gpu_match}
+
+
+def sweep(torch, aes, inputs, sizes):
+    out = {}
+    buf_in = inputs.device_random_bytes(3, max(sizes))
+    buf_out = torch.empty_like(buf_in)
+    for keybits in (128, 192, 256):
+        ks = aes.aes_expand_key(inputs.random_key(3, keybits))
+        for dec in (False, True):
+            for n in sizes:
+                xi, xo = buf_in[:n], buf_out[:n]
+                fn = (lambda: aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, xi, xo)) if dec else \
+                     (lambda: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xi, xo))
+                reps = max(3, min(50, int(4 * GiB / n)))
+                fn()
+                tm = Timer(torch)
+                for _ in range(reps):
+                    tm.run(fn)
+                ms = sorted(tm.ms())[reps // 2]
+                out["aes%d_%s_%s" % (keybits, "dec" if dec else "enc", size_name(n))] = round(n / (ms * 1e-3) / 1e9, 1)
+    del buf_in, buf_out
+    torch.cuda.empty_cache()
+    return out
+
+
+def size_name(n):
+    return "%dGiB" % (n // GiB) if n >= GiB else "%dMiB" % (n // MiB)
+
+
+def batched(torch, aes, inputs, bulk_rates):
+    from paper_1902_05234_amd import batch
+    mix = inputs.message_mix(2, 20000)
+    keys = [inputs.random_key(int(s), int(b)) for s, b in zip(mix.key_seed, mix.keybits)]
+    kt = batch.key_table(keys)
+    total = mix.total_blocks
+    in_arena = inputs.device_random_bytes(2, 16 * total)
+    out_arena = torch.empty_like(in_arena)
+    b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=1024)
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    for _ in range(5):
+        tm.run(b.replay)
+    ms = sorted(tm.ms())[2]
+    nbytes = 16 * total
+    batched_gbps = nbytes / (ms * 1e-3) / 1e9
+    # per-message plain launches, same arenas, same bytes
+    scheds = [aes.aes_expand_key(k) for k in keys]
+    batch.run_per_message(b.msgs, scheds, in_arena, out_arena)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run_per_message(b.msgs, scheds, in_arena, out_arena)
+    torch.cuda.synchronize()
+    per_msg_s = time.perf_counter() - t0
+    # bulk-equivalent: each (key size, direction) share at its 1 GiB bulk rate
+    t_eq = 0.0
+    for kb in (128, 192, 256):
+        for dec in (False, True):
+            sel = (mix.keybits == kb) & (mix.decrypt == dec)
+            t_eq += 16 * int(mix.nblocks[sel].sum()) / (bulk_rates["aes%d_%s_1GiB" % (kb, "dec" if dec else "enc")] * 1e9)
+    bulk_eq = nbytes / t_eq / 1e9
+    return {"messages": len(mix), "bytes": nbytes, "GB_s": round(batched_gbps, 1), "ms": round(ms, 3),
+            "bulk_equivalent_GB_s": round(bulk_eq, 1), "vs_bulk": round(batched_gbps / bulk_eq, 4),
+            "per_message_launch_GB_s": round(nbytes / per_msg_s / 1e9, 2),
+            "rejected_items": b.rejected_items(), "chunk_blocks": 1024, "graph": True}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile", action="store_true", help="only a few copy and bulk launches (for rocprofv3)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: ECB blocks are independent, so N GPUs would each run this same "
+              "single-GPU kernel on 1/N of the buffer with no communication; only --gpus 1 is supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1902_05234_amd import aes, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    aes._lib()
+    props = torch.cuda.get_device_properties(0)
+    log("device:", props.name, "CUs:", props.multi_processor_count)
+
+    if args.profile:
+        x = inputs.device_random_bytes(1, GiB)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            aes.aes_device_copy(x, y)
+        ks = aes.aes_expand_key(inputs.random_key(1, 128))
+        for _ in range(max(1, args.steps)):
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
+            aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, y, x)
+        torch.cuda.synchronize()
+        log("profile launches done")
+        return
+
+    b = bulk(torch, aes, inputs, args)
+    log("bulk: %.3f s for %d steps" % (b["elapsed"], args.steps))
+    traffic = read_traffic(b["nbytes"])
+    result = {
+        "metric": "AES-ECB enc/dec GB/s at 1 GiB + % roofline; batched vs plain GB/s; p99 latency",
+        "value": round(2 * b["nbytes"] * args.steps / b["elapsed"] / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(b["elapsed"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "AES-128 ECB encrypt then decrypt of one 1 GiB device buffer (67,108,864 blocks), "
+                               "seeded uniform random bytes and key", "keybits": 128, "bytes": b["nbytes"],
+                   "parallelism": "single GPU"},
+        "enc_GB_s": round(b["nbytes"] / (sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3) / 1e9, 1),
+        "dec_GB_s": round(b["nbytes"] / (sum(b["dec_ms"]) / len(b["dec_ms"]) * 1e-3) / 1e9, 1),
+        "roofline": roofline(b, traffic),
+        "kernel_source_hash": kernel_source_hash(),
+        "device": props.name,
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(b, args)
+        log("cpu baseline done")
+    del b
+    torch.cuda.empty_cache()
+    rates = None
+    if not args.no_sweep or not args.no_batch:
+        sizes = [MiB, 16 * MiB, 256 * MiB, GiB] + ([] if args.no_sweep else [4 * GiB])
+        rates = sweep(torch, aes, inputs, sizes)
+        log("sweep done")
+        if not args.no_sweep:
+            result["sweep_GB_s"] = rates
+    if not args.no_batch:
+        result["batched"] = batched(torch, aes, inputs, rates)
+        log("batched done")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

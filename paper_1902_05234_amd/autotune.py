@@ -1,0 +1,169 @@
+"""Autotuner for the plain and batched ECB kernels.
+
+Search space (plain path): blocks per thread {1, 2, 4} (16/32/64 bytes per
+thread) x workgroup size {64, 128, 256, 512, 1024} x table placement (the
+placements built into the library).  Every variant must reproduce the
+reference variant's output bit for bit (and decrypt back to the input)
+before it is timed.  The winner of each (key size, direction, size bucket)
+is written to a JSON record keyed by device and library source hash and can
+be installed into the library's tuning table with ``apply``.
+
+Batched path: chunk size (blocks per work item) x blocks per thread.
+
+    python -m paper_1902_05234_amd.autotune --out tune.json
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+from . import aes, inputs
+
+BPTS = (1, 2, 4)
+WGS = (64, 128, 256, 512, 1024)
+PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4,)
+# representative sizes of the tuning buckets (bytes)
+BUCKET_SIZES = (4 << 10, 64 << 10, 1 << 20, 8 << 20, 256 << 20)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _time(torch, fn, reps):
+    fn()
+    s = torch.cuda.current_stream()
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    return ms[len(ms) // 2]
+
+
+def variants():
+    for p in PLACEMENTS:
+        for b in BPTS:
+            for w in WGS:
+                yield aes.Variant(bpt=b, wg=w, placement=p)
+
+
+def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, log=print):
+    """Time every variant on one (key size, direction, size); returns rows sorted by time."""
+    key = inputs.random_key(7, keybits)
+    ks = aes.aes_expand_key(key)
+    x = inputs.device_random_bytes(7, nbytes)
+    ref = torch.empty_like(x)
+    rk = ks.rk_dec if decrypt else ks.rk_enc
+    aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, ref, aes.Variant())
+    back = torch.empty_like(x)
+    inv = ks.rk_enc if decrypt else ks.rk_dec
+    aes.aes_ecb_crypt_variant(inv, ks.nr, not decrypt, ref, back, aes.Variant())
+    torch.cuda.synchronize()
+    if not torch.equal(back, x):
+        raise RuntimeError("reference variant does not round-trip")
+    rows = []
+    out = torch.empty_like(x)
+    for v in variants():
+        out.zero_()
+        aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v)
+        torch.cuda.synchronize()
+        if not torch.equal(out, ref):
+            raise RuntimeError("variant %s differs from the reference output" % (v,))
+        ms = _time(torch, lambda: aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v), reps)
+        rows.append({"bpt": v.bpt, "wg": v.wg, "placement": v.placement, "ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9})
+    rows.sort(key=lambda r: r["ms"])
+    log("  %d-bit %s %d B: best bpt=%d wg=%d %.1f GB/s (worst %.1f)" % (
+        keybits, "dec" if decrypt else "enc", nbytes, rows[0]["bpt"], rows[0]["wg"], rows[0]["GB_s"], rows[-1]["GB_s"]))
+    return rows
+
+
+def tune_batch(torch, n_messages: int = 20000, chunks=(256, 1024, 4096), reps: int = 5, log=print):
+    from . import batch
+    mix = inputs.message_mix(2, n_messages)
+    keys = [inputs.random_key(int(s), int(b)) for s, b in zip(mix.key_seed, mix.keybits)]
+    kt = batch.key_table(keys)
+    in_arena = inputs.device_random_bytes(2, 16 * mix.total_blocks)
+    out_arena = torch.empty_like(in_arena)
+    ref = None
+    rows = []
+    for chunk in chunks:
+        for bpt in BPTS:
+            b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=chunk,
+                              cfg=aes.BatchConfig(bpt=bpt))
+            out_arena.zero_()
+            b.launch()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out_arena.clone()
+            elif not torch.equal(out_arena, ref):
+                raise RuntimeError("batch chunk=%d bpt=%d differs from the first configuration" % (chunk, bpt))
+            ms = _time(torch, b.launch, reps)
+            rows.append({"chunk_blocks": chunk, "bpt": bpt, "ms": ms, "GB_s": b.total_bytes / (ms * 1e-3) / 1e9})
+            log("  batch chunk=%d bpt=%d: %.1f GB/s" % (chunk, bpt, rows[-1]["GB_s"]))
+    rows.sort(key=lambda r: r["ms"])
+    return rows
+
+
+def run(sizes=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, log=print):
+    import torch
+    rec = {"device": torch.cuda.get_device_properties(0).name, "source_hash": source_hash(),
+           "created": time.strftime("%Y-%m-%dT%H:%M:%S"), "plain": {}, "batch": None}
+    for kb in key_sizes:
+        for dec in (False, True):
+            for n in sizes:
+                rows = tune_plain(torch, kb, dec, n, reps=reps, log=log)
+                rec["plain"]["%d/%s/%d" % (kb, "dec" if dec else "enc", n)] = {"winner": rows[0], "all": rows}
+    if batch_too:
+        rec["batch"] = tune_batch(torch, log=log)
+    return rec
+
+
+def apply(record: dict):
+    """Install the plain-path winners of a record into the library's tuning table."""
+    n = 0
+    for k, v in record.get("plain", {}).items():
+        kb, d, nbytes = k.split("/")
+        w = v["winner"]
+        nr = {128: 10, 192: 12, 256: 14}[int(kb)]
+        aes.aes_tune_set(nr, d == "dec", int(nbytes) // 16, aes.Variant(w["bpt"], w["wg"], w["placement"]))
+        n += 1
+    return n
+
+
+def load(path: str) -> dict:
+    with open(path) as f:
+        return json.load(f)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", default="aesgpu_tune.json")
+    ap.add_argument("--quick", action="store_true", help="AES-256 decrypt of 256 MiB plus the batch mix only")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args(argv)
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    if a.quick:
+        rec = run(sizes=(256 << 20,), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, log=log)
+    else:
+        rec = run(batch_too=not a.no_batch, reps=a.reps, log=log)
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    log("wrote", a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,19 @@ struct TuneEntry {
 };
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
+// Compiled-in defaults (MI355X sweep): more blocks per thread pays once the
+// buffer fills every CU many times over.
+struct TuneDefaults {
+    TuneDefaults()
+    {
+        for (auto& nr : g_tune)
+            for (auto& dir : nr) {
+                dir[3].bpt.store(2);
+                dir[4].bpt.store(4);
+            }
+    }
+} g_tune_defaults;
+
 int nr_index(int nr) { return (nr - 10) / 2; }
 
 std::atomic<int> g_cu_count[64];

@@ -84,7 +84,7 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
         const uint32_t slot = __builtin_amdgcn_readfirstlane(it.key_slot);
         const bool ok = slot < n_slots && in_b <= in_blocks && nb <= in_blocks - in_b && out_b <= out_blocks &&
                         nb <= out_blocks - out_b;
-        const uint32_t* kp = key_table + (uint64_t)slot * kSlotWords;
+        const uint32_t* kp = key_table + (uint64_t)(ok ? slot : 0u) * kSlotWords;
         const int nr = ok ? (int)__builtin_amdgcn_readfirstlane(kp[kSlotNr]) : 0;
         const uint32_t* kd = kp + (kDecrypt ? 64 : 0);
         switch (nr) {

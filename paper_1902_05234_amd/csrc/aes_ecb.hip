@@ -32,29 +32,36 @@ __global__ __launch_bounds__(1024) void ecb_kernel(const uint4* __restrict__ in,
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves_per_grid = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t span = 64u * BPT;
-    for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv * span < nblocks;
-         wv += waves_per_grid) {
+    uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // The next unit's blocks are loaded before the current unit is
+    // encrypted, so the HBM latency of one unit hides behind the rounds of
+    // the previous one.  Blocks past the end are neither loaded nor stored.
+    uint4 cur[BPT];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const uint64_t b = wv * span + lane + 64u * k;
+        cur[k] = b < nblocks ? in[b] : make_uint4(0, 0, 0, 0);
+    }
+    while (wv * span < nblocks) {
         const uint64_t first = wv * span + lane;
-        if (first + 64u * (BPT - 1) < nblocks) {
-            uint4 x[BPT];
+        const uint64_t wn = wv + waves_per_grid;
+        uint4 nxt[BPT];
 #pragma unroll
-            for (int k = 0; k < BPT; ++k)
-                x[k] = in[first + 64u * k];
-#pragma unroll
-            for (int k = 0; k < BPT; ++k)
-                x[k] = crypt_block<NR, kDecrypt>(x[k], lds, lb, key);
-#pragma unroll
-            for (int k = 0; k < BPT; ++k)
-                out[first + 64u * k] = x[k];
-        } else {
-            // ragged tail of the buffer
-#pragma unroll
-            for (int k = 0; k < BPT; ++k) {
-                uint64_t b = first + 64u * k;
-                if (b < nblocks)
-                    out[b] = crypt_block<NR, kDecrypt>(in[b], lds, lb, key);
-            }
+        for (int k = 0; k < BPT; ++k) {
+            const uint64_t b = wn * span + lane + 64u * k;
+            nxt[k] = b < nblocks ? in[b] : make_uint4(0, 0, 0, 0);
         }
+#pragma unroll
+        for (int k = 0; k < BPT; ++k)
+            cur[k] = crypt_block<NR, kDecrypt>(cur[k], lds, lb, key);
+#pragma unroll
+        for (int k = 0; k < BPT; ++k)
+            if (first + 64u * k < nblocks)
+                out[first + 64u * k] = cur[k];
+#pragma unroll
+        for (int k = 0; k < BPT; ++k)
+            cur[k] = nxt[k];
+        wv = wn;
     }
 }
 

@@ -206,11 +206,12 @@ def test_tuning_table_round_trip():
     for nr in (10, 12, 14):
         for dec in (False, True):
             for nb in (1, 300, 5000, 70000, 1 << 22):
+                old = aes.aes_tune_get(nr, dec, nb)
                 v = aes.Variant(bpt=2, wg=512)
                 aes.aes_tune_set(nr, dec, nb, v)
                 got = aes.aes_tune_get(nr, dec, nb)
                 assert (got.bpt, got.wg, got.placement) == (2, 512, aes.AES_PLACEMENT_TTABLE4)
-                aes.aes_tune_set(nr, dec, nb, aes.Variant())
+                aes.aes_tune_set(nr, dec, nb, old)
     assert [aes.aes_size_bucket(n) for n in (1, 256, 257, 4096, 4097, 65536, 65537, 524288, 524289)] == [0, 0, 1, 1, 2, 2, 3, 3, 4]
     with pytest.raises(aes.AesError):
         aes.aes_tune_set(10, False, 1, aes.Variant(bpt=8))
