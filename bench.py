@@ -16,6 +16,9 @@ before timing starts.  Prints ONE JSON line:
   batched      20,000 mixed messages in one persistent launch (graph replay)
                vs per-message plain launches and vs the bulk-equivalent rate
   sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB
+  serving      open-loop Poisson requests (80 % 64 B-16 KiB, 20 % 1-64 MiB,
+               4,096 resident keys, 32 GiB device budget) at offered loads
+               rho x the batched rate: p50/p99 latency and sustained GB/s
 
 Flags: --gpus N (only 1 is supported), --steps K, --warmup W,
 --no-batch / --no-sweep / --no-cpu to skip sections, --profile to run only a
@@ -135,8 +138,10 @@ def bulk(torch, aes, inputs, args):
     return dict(key=key, x=x, c=c, nbytes=nbytes, elapsed=elapsed, enc_ms=enc_ms, dec_ms=dec_ms)
 
 
-def roofline(b, traffic):
+def roofline(b, traffic, aes):
     nblocks = b["nbytes"] // 16
+    v = aes.aes_tune_get(10, False, nblocks)
+    places = {0: "4 tables", 1: "2 tables", 2: "1 table"}
     t = sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3
     nr = 10
     lookups = lookups_per_block(nr) * nblocks
@@ -144,7 +149,8 @@ def roofline(b, traffic):
     peak = LDS_PEAK / 1e9
     hbm_alg = 32 * nblocks
     return {
-        "kernel": "ecb_kernel<Nr=10, encrypt, 16 B/thread>",
+        "kernel": "ecb_kernel<Nr=10, encrypt, %d B/thread, %s in LDS, %d-thread workgroups>" % (
+            16 * v.bpt, places.get(v.placement, "?"), v.wg),
         "bound": "lds",
         "achieved": round(ach, 1),
         "peak": round(peak, 1),
@@ -264,6 +270,37 @@ def batched(torch, aes, inputs, bulk_rates):
             "rejected_items": b.rejected_items(), "chunk_blocks": 1024, "graph": True}
 
 
+def serving(torch, aes, inputs, peak_gbps, levels, n_req):
+    """Open-loop Poisson arrivals at offered loads rho x peak; p50/p99 latency
+    (arrival -> completion observed on the host) and sustained GB/s."""
+    from paper_1902_05234_amd import batch
+    from paper_1902_05234_amd.serve import GpuExecutor, Scheduler, requests_from_trace, run_trace
+    pool = inputs.key_pool(4, 4096)
+    kt = batch.key_table([k for _, k in pool])
+    pool_bytes = 4 * GiB
+    in_pool = inputs.device_random_bytes(4, pool_bytes)
+    budget = 32 * GiB
+    out_arena = torch.empty(budget // 2, dtype=torch.uint8, device="cuda")
+    mean_b = inputs.mean_trace_bytes()
+    rows = []
+    for k, rho in enumerate(levels):
+        rate = rho * peak_gbps * 1e9 / mean_b
+        trace = inputs.request_trace(100 + k, n_req, rate, len(pool))
+        reqs = requests_from_trace(trace, pool_bytes // 16, seed=k)
+        sch = Scheduler(budget, out_arena.numel() // 16, chunk_blocks=1024, max_batch_items=1 << 18)
+        ex = GpuExecutor(kt, in_pool, out_arena, nslots=4, max_items=1 << 18, chunk_blocks=1024)
+        stats = run_trace(sch, ex, reqs)
+        row = {"rho": rho, "offered_GB_s": round(rho * peak_gbps, 1)}
+        row.update(stats.summary())
+        rows.append(row)
+        log("serving rho=%.2f: p50 %.3f ms p99 %.3f ms %.1f GB/s" % (rho, row["p50_ms"], row["p99_ms"], row["GB_s"]))
+        del ex
+    del in_pool, out_arena
+    torch.cuda.empty_cache()
+    return {"peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget, "key_pool": len(pool),
+            "mean_request_bytes": round(mean_b), "streams": 4, "levels": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +310,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-levels", default="0.3,0.6,0.9")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--profile", action="store_true", help="only a few copy and bulk launches (for rocprofv3)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -326,7 +366,7 @@ def main():
                    "parallelism": "single GPU"},
         "enc_GB_s": round(b["nbytes"] / (sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3) / 1e9, 1),
         "dec_GB_s": round(b["nbytes"] / (sum(b["dec_ms"]) / len(b["dec_ms"]) * 1e-3) / 1e9, 1),
-        "roofline": roofline(b, traffic),
+        "roofline": roofline(b, traffic, aes),
         "kernel_source_hash": kernel_source_hash(),
         "device": props.name,
     }
@@ -345,6 +385,11 @@ def main():
     if not args.no_batch:
         result["batched"] = batched(torch, aes, inputs, rates)
         log("batched done")
+    if not args.no_serve:
+        peak = result["batched"]["GB_s"] if "batched" in result else result["value"]
+        levels = [float(v) for v in args.serve_levels.split(",") if v]
+        result["serving"] = serving(torch, aes, inputs, peak, levels, args.serve_requests)
+        log("serving done")
     print(json.dumps(result), flush=True)
 
 

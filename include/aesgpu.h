@@ -80,12 +80,14 @@ int aes_ecb_encrypt(const uint32_t *rk, int nr, const void *in, void *out, size_
 int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_t nblocks, void *stream);
 
 /* Kernel variant of the plain path (the autotuner's search space). */
-#define AES_PLACEMENT_TTABLE4 0 /* four T-tables, 32 replicas each, in LDS */
+#define AES_PLACEMENT_TTABLE4 0 /* four T-tables, 32 replicas each, in LDS (128 KiB) */
+#define AES_PLACEMENT_TTABLE2 1 /* T0 and T2 (= T0 rotated 16), 32 replicas (64 KiB) */
+#define AES_PLACEMENT_TTABLE1 2 /* T0 only, 32 replicas (32 KiB); rotations on the VALU */
 typedef struct {
     int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes) */
     int32_t wg;        /* workgroup size: multiple of 64 in [64, 1024] */
     int32_t placement; /* AES_PLACEMENT_* */
-    int32_t grid;      /* workgroups; 0 = one per compute unit (persistent) */
+    int32_t grid;      /* workgroups; 0 = persistent (compute units x workgroups that fit on one) */
 } aes_variant;
 
 /* Same as aes_ecb_encrypt/decrypt (decrypt != 0 selects decryption) with an

@@ -26,7 +26,7 @@ from . import aes, inputs
 
 BPTS = (1, 2, 4)
 WGS = (64, 128, 256, 512, 1024)
-PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4,)
+PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1)
 # representative sizes of the tuning buckets (bytes)
 BUCKET_SIZES = (4 << 10, 64 << 10, 1 << 20, 8 << 20, 256 << 20)
 

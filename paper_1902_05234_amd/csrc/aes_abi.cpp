@@ -82,16 +82,28 @@ struct TuneEntry {
 };
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
-// Compiled-in defaults (MI355X sweep): more blocks per thread pays once the
-// buffer fills every CU many times over.
+// Compiled-in defaults from an MI355X autotune sweep (paper_1902_05234_amd.autotune):
+// small buffers are launch-bound and prefer the smallest table fill; large
+// encryptions prefer the 2-table placement at two 1024-thread workgroups per
+// CU, large decryptions the 4-table placement with 4 blocks per thread.
 struct TuneDefaults {
+    static void set(TuneEntry& t, int bpt, int wg, int placement)
+    {
+        t.bpt.store(bpt);
+        t.wg.store(wg);
+        t.placement.store(placement);
+    }
     TuneDefaults()
     {
-        for (auto& nr : g_tune)
-            for (auto& dir : nr) {
-                dir[3].bpt.store(2);
-                dir[4].bpt.store(4);
+        for (int n = 0; n < 3; ++n) {
+            for (int d = 0; d < 2; ++d) {
+                for (int b = 0; b < 3; ++b)
+                    set(g_tune[n][d][b], 1, 512, AES_PLACEMENT_TTABLE1);
+                set(g_tune[n][d][3], 2, 1024, AES_PLACEMENT_TTABLE2);
             }
+            set(g_tune[n][0][4], n == 0 ? 2 : 4, 1024, AES_PLACEMENT_TTABLE2);
+            set(g_tune[n][1][4], n == 1 ? 2 : 4, 1024, AES_PLACEMENT_TTABLE4);
+        }
     }
 } g_tune_defaults;
 
@@ -126,7 +138,8 @@ int check_variant(const aes_variant* v)
         return fail(AES_EINVAL, "bpt must be 1, 2 or 4 (16, 32 or 64 bytes per thread), got %d", v->bpt);
     if (v->wg < 64 || v->wg > 1024 || (v->wg % 64) != 0)
         return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", v->wg);
-    if (v->placement != AES_PLACEMENT_TTABLE4)
+    if (v->placement != AES_PLACEMENT_TTABLE4 && v->placement != AES_PLACEMENT_TTABLE2 &&
+        v->placement != AES_PLACEMENT_TTABLE1)
         return fail(AES_EINVAL, "placement %d is not built in this library", v->placement);
     if (v->grid < 0)
         return fail(AES_EINVAL, "grid must be >= 0 (0 = persistent default), got %d", v->grid);
@@ -153,13 +166,9 @@ int run_ecb(const uint32_t* rk, int nr, bool decrypt, const void* in, void* out,
     int cus = device_cu_count();
     if (cus <= 0)
         return fail(AES_EHIP, "cannot query the current HIP device");
-    const uint64_t per_group = (uint64_t)v->wg * (uint64_t)v->bpt;
-    const uint64_t needed = (nblocks + per_group - 1) / per_group;
-    // one workgroup per CU: the replicated tables use 128-160 KiB of LDS
-    uint64_t grid = v->grid > 0 ? (uint64_t)v->grid : (uint64_t)cus;
-    grid = std::min<uint64_t>(grid, needed);
-    LaunchShape shape{v->bpt, v->wg, (int)grid};
-    hipError_t e = launch_ecb(shape, nr, decrypt, in, out, nblocks, keys, static_cast<hipStream_t>(stream));
+    LaunchShape shape{v->bpt, v->wg, v->grid};
+    hipError_t e =
+        launch_ecb(shape, v->placement, nr, decrypt, in, out, nblocks, keys, cus, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "ECB kernel launch");
     return AES_OK;

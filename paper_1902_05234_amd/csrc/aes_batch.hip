@@ -28,7 +28,8 @@ constexpr int kSlotNr = 124;
 
 template <int NR, bool kDecrypt, int BPT>
 __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __restrict__ out, uint32_t nblocks,
-                                         const uint32_t* lds, const LaneBases& lb, const uint32_t* __restrict__ kp)
+                                         const uint32_t* lds, const LaneBases<kPlace4, kDecrypt>& lb,
+                                         const uint32_t* __restrict__ kp)
 {
     uint32_t k[4 * (NR + 1)];
 #pragma unroll
@@ -45,7 +46,7 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
                 x[j] = in[first + 64u * j];
 #pragma unroll
             for (int j = 0; j < BPT; ++j)
-                x[j] = crypt_block<NR, kDecrypt>(x[j], lds, lb, key);
+                x[j] = crypt_block<NR, kDecrypt, kPlace4>(x[j], lds, lb, key);
 #pragma unroll
             for (int j = 0; j < BPT; ++j)
                 out[first + 64u * j] = x[j];
@@ -54,7 +55,7 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
             for (int j = 0; j < BPT; ++j) {
                 uint32_t b = first + 64u * j;
                 if (b < nblocks)
-                    out[b] = crypt_block<NR, kDecrypt>(in[b], lds, lb, key);
+                    out[b] = crypt_block<NR, kDecrypt, kPlace4>(in[b], lds, lb, key);
             }
         }
     }
@@ -65,9 +66,10 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
                                       const uint32_t* __restrict__ key_table, uint32_t n_slots,
                                       const uint4* __restrict__ in_base, uint4* __restrict__ out_base,
                                       uint64_t in_blocks, uint64_t out_blocks, uint32_t* counters,
-                                      const uint32_t* lds, const LaneBases& lb)
+                                      const uint32_t* lds)
 {
     const uint32_t lane = threadIdx.x & 63u;
+    const LaneBases<kPlace4, kDecrypt> lb(threadIdx.x);
     for (;;) {
         uint32_t idx = 0;
         if (lane == 0)
@@ -106,21 +108,20 @@ __global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict_
                                                      uint4* __restrict__ out_base, uint64_t in_blocks,
                                                      uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups)
 {
-    __shared__ uint32_t lds[kDecLdsWords];
-    const LaneBases lb(threadIdx.x);
+    __shared__ uint32_t lds[Layout<kPlace4, true>::words];
     bool dec = blockIdx.x >= enc_groups;
     for (int pass = 0; pass < 2; ++pass, dec = !dec) {
         if (dec)
-            fill_tables<true>(lds, &c_tables);
+            fill_tables<kPlace4, true>(lds, &c_tables);
         else
-            fill_tables<false>(lds, &c_tables);
+            fill_tables<kPlace4, false>(lds, &c_tables);
         __syncthreads();
         if (dec)
             drain<true, BPT>(items, n_enc, n_dec, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
-                             counters, lds, lb);
+                             counters, lds);
         else
             drain<false, BPT>(items, 0, n_enc, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
-                              counters, lds, lb);
+                              counters, lds);
         __syncthreads();  // every wave is done with these tables before LDS is refilled
     }
     if (threadIdx.x == 0) {

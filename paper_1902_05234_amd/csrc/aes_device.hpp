@@ -9,19 +9,33 @@
 //   dec: e_j = Td0[b0(W_j)]  ^ Td1[b1(W_{j-1})] ^ Td2[b2(W_{j-2})] ^ Td3[b3(W_{j-3})] ^ k_j
 // (decryption is the equivalent inverse cipher of FIPS-197 5.3.5: the round
 // keys of rounds 1..Nr-1 have InvMixColumns applied, see aes_expand_key.)
-// Final round has no MixColumns: enc takes the S-box byte from the T-table
-// whose byte t is {01}s (T2 row 0, T3 row 1, T0 row 2, T1 row 3); dec uses Si4.
+// With little-endian column words T_k = rotl(T_0, 8k).  The final round has
+// no MixColumns: encryption takes the S-box byte from a T-table whose byte t
+// is {01}s (T0 has it in bytes 1 and 2, T2 in bytes 0 and 3); decryption
+// reads a replicated InvS table.
 //
-// LDS layout (gfx950 LDS: 32 banks of 4 bytes; a wave64 ds_read_b32 is served
-// 32 lanes per clock, so 32 replicas make any lookup pattern conflict free):
-//   table t, entry e, replica r at byte  (t & 1) * 65536 + e * 256 + (t >> 1) * 128 + r * 4
-//   Si4 (decryption only), entry e, replica r at byte  131072 + e * 128 + r * 4
-// Lane l reads replica r = l mod 32, so every access of one instruction falls
-// in bank l mod 32.  With the entry index in address bits 8..15, an address is
-// (byte of W shifted to bits 8..15) | base_t, built with one or two of the
-// instructions gfx950 issues at full rate (v_bitop3_b32 with VGPR operands,
-// v_lshlrev_b16, v_lshrrev_b32, v_or_b32).  v_perm_b32, v_bfe_u32, SDWA forms
-// and any VALU form with an SGPR operand issue at about half that rate.
+// gfx950 LDS has 32 banks of 4 bytes and serves a wave64 ds_read_b32 32 lanes
+// per clock, so a table replicated 32 times, with lane l reading replica
+// l mod 32, is conflict free for any data.  Three placements of the tables in
+// LDS trade LDS size (and so workgroups per CU) against VALU work:
+//
+//   4 tables  T0..T3, 32 replicas each: 128 KiB.  Table t, entry e, replica r
+//             at byte (t & 1) * 65536 + e * 256 + (t >> 1) * 128 + r * 4.
+//   2 tables  T0 and T2 = rotl(T0, 16): 64 KiB, at e * 256 + h * 128 + r * 4
+//             (h = 0 for T0, 1 for T2); T1/T3 terms are summed and rotated
+//             by 8 once per column.
+//   1 table   T0 only: 32 KiB at e * 128 + r * 4; three rotations per column.
+//
+// InvS for the last decryption round follows the tables: word-wide (InvS in
+// all four bytes, e * 128 + r * 4, 32 KiB) with 4 tables, byte-packed
+// ((e >> 2) * 128 + r * 4 + (e & 3), 8 KiB) with 1 or 2 tables.
+//
+// Lookup addresses put the state byte into bits 8..15 (stride 256) or 7..14
+// (stride 128) and OR in the lane's base, using the VALU forms gfx950 issues
+// at full rate (v_bitop3_b32 with VGPR operands, v_lshlrev_b16,
+// v_lshrrev_b32, v_or_b32).  v_perm_b32, v_bfe_u32, v_and_or_b32, SDWA forms
+// and any form with an SGPR operand issue at about half that rate, which is
+// why the address code is written with inline v_bitop3_b32 / v_lshlrev_b16.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -30,11 +44,17 @@
 
 namespace aesgpu {
 
-constexpr uint32_t kTableBytes = 131072;        // four 1 KiB tables x 32 replicas
-constexpr uint32_t kSi4Offset = 131072;
-constexpr uint32_t kSi4Bytes = 32768;           // 256 entries x 32 replicas x 4 B
-constexpr uint32_t kEncLdsWords = kTableBytes / 4;
-constexpr uint32_t kDecLdsWords = (kTableBytes + kSi4Bytes) / 4;
+constexpr int kPlace4 = 0;  // values match AES_PLACEMENT_* in aesgpu.h
+constexpr int kPlace2 = 1;
+constexpr int kPlace1 = 2;
+
+template <int PL, bool kDecrypt>
+struct Layout {
+    static constexpr uint32_t table_bytes = PL == kPlace4 ? 131072u : PL == kPlace2 ? 65536u : 32768u;
+    static constexpr uint32_t si_offset = table_bytes;
+    static constexpr uint32_t si_bytes = !kDecrypt ? 0u : PL == kPlace4 ? 32768u : 8192u;
+    static constexpr uint32_t words = (table_bytes + si_bytes) / 4;
+};
 
 // Source tables in constant memory (one copy per translation unit).
 static __constant__ TableSet c_tables = make_tables();
@@ -54,131 +74,229 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return d;
 }
 
-__device__ __forceinline__ uint32_t shl16_by8(uint32_t a)
+// a ^ b ^ k with k uniform: k stays in an SGPR.  This is the half-rate form,
+// but it keeps the round keys out of VGPRs (44-60 of them otherwise), which
+// leaves room for more resident waves; the cost is 4 instructions per round.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 {
-    uint32_t d;  // (a << 8) & 0xffff: byte 0 moved to bits 8..15
-    asm("v_lshlrev_b16 %0, 8, %1" : "=v"(d) : "v"(a));
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
     return d;
 }
 
-__device__ __forceinline__ uint32_t shl16_by7(uint32_t a)
+template <int N>
+__device__ __forceinline__ uint32_t shl16(uint32_t a)
 {
-    uint32_t d;  // (a << 7) & 0xffff
-    asm("v_lshlrev_b16 %0, 7, %1" : "=v"(d) : "v"(a));
+    uint32_t d;  // (a << N) & 0xffff
+    asm("v_lshlrev_b16 %0, %2, %1" : "=v"(d) : "v"(a), "i"(N));
     return d;
 }
+
+__device__ __forceinline__ uint32_t rotl8(uint32_t y) { return (y << 8) | (y >> 24); }
 
 __device__ __forceinline__ uint32_t lds_word(const uint32_t* lds, uint32_t byte_addr)
 {
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(lds) + byte_addr);
 }
 
+__device__ __forceinline__ uint32_t lds_byte(const uint32_t* lds, uint32_t byte_addr)
+{
+    return *(reinterpret_cast<const uint8_t*>(lds) + byte_addr);
+}
+
 // Per-lane constants of the lookup addresses.
+template <int PL, bool kDecrypt>
 struct LaneBases {
-    uint32_t b[4];   // base of table t for this lane's replica
-    uint32_t bs;     // base of Si4 for this lane's replica
-    uint32_t m8;     // 0x0000ff00
-    uint32_t m7;     // 0x00007f80
-    uint32_t m16;    // 0x00ff0000
-    uint32_t m24;    // 0xff000000
+    uint32_t b[4];   // base used for state byte t in an inner round
+    uint32_t f[4];   // base used for state byte t in the last (encryption) round
+    uint32_t bs;     // InvS base
+    uint32_t m8, m7, m16, m24, m3, m1f80;
 
     __device__ __forceinline__ explicit LaneBases(uint32_t lane)
     {
-        uint32_t r4 = (lane & 31u) << 2;
-        for (int t = 0; t < 4; ++t)
-            b[t] = ((uint32_t(t) & 1u) << 16) | ((uint32_t(t) >> 1) << 7) | r4;
-        bs = kSi4Offset | r4;
-        // opaque copies keep these in VGPRs so every bitop3 operand is a VGPR
+        const uint32_t r4 = (lane & 31u) << 2;
+        if (PL == kPlace4) {
+            for (int t = 0; t < 4; ++t)
+                b[t] = ((uint32_t(t) & 1u) << 16) | ((uint32_t(t) >> 1) << 7) | r4;
+            // byte t of the last-round result comes from T_{t+2}
+            f[0] = b[2], f[1] = b[3], f[2] = b[0], f[3] = b[1];
+        } else if (PL == kPlace2) {
+            b[0] = b[1] = r4;                // T0
+            b[2] = b[3] = 128u | r4;         // T2
+            f[0] = f[3] = 128u | r4;         // T2 has {01}s in bytes 0 and 3
+            f[1] = f[2] = r4;                // T0 has {01}s in bytes 1 and 2
+        } else {
+            for (int t = 0; t < 4; ++t)
+                b[t] = f[t] = r4;
+        }
+        bs = Layout<PL, kDecrypt>::si_offset | r4;
+        // opaque copies keep the masks in VGPRs so every bitop3 operand is a VGPR
         asm volatile("v_mov_b32 %0, 0xff00" : "=v"(m8));
         asm volatile("v_mov_b32 %0, 0x7f80" : "=v"(m7));
         asm volatile("v_mov_b32 %0, 0xff0000" : "=v"(m16));
         asm volatile("v_mov_b32 %0, 0xff000000" : "=v"(m24));
+        asm volatile("v_mov_b32 %0, 3" : "=v"(m3));
+        asm volatile("v_mov_b32 %0, 0x1f80" : "=v"(m1f80));
     }
 };
 
 // Fill the replicated tables of one direction into LDS (whole workgroup).
-template <bool kDecrypt>
+template <int PL, bool kDecrypt>
 __device__ __forceinline__ void fill_tables(uint32_t* lds, const TableSet* __restrict__ tabs)
 {
+    using L = Layout<PL, kDecrypt>;
     const uint32_t* src = kDecrypt ? tabs->td0 : tabs->te0;
-    for (uint32_t w = threadIdx.x; w < kEncLdsWords; w += blockDim.x) {
-        uint32_t region = w >> 14, e = (w >> 6) & 255u, half = (w >> 5) & 1u;
-        uint32_t t = region | (half << 1);
-        uint32_t v = src[e];
+    for (uint32_t w = threadIdx.x; w < L::table_bytes / 4; w += blockDim.x) {
+        uint32_t e, t;
+        if (PL == kPlace4) {
+            e = (w >> 6) & 255u;
+            t = (w >> 14) | (((w >> 5) & 1u) << 1);
+        } else if (PL == kPlace2) {
+            e = w >> 6;
+            t = ((w >> 5) & 1u) << 1;
+        } else {
+            e = w >> 5;
+            t = 0;
+        }
+        const uint32_t v = src[e];
         lds[w] = t ? ((v << (8 * t)) | (v >> (32 - 8 * t))) : v;
     }
     if (kDecrypt) {
-        for (uint32_t w = threadIdx.x; w < kSi4Bytes / 4; w += blockDim.x)
-            lds[kSi4Offset / 4 + w] = tabs->si4[w >> 5];
+        for (uint32_t w = threadIdx.x; w < L::si_bytes / 4; w += blockDim.x) {
+            uint32_t v;
+            if (PL == kPlace4) {
+                v = tabs->si4[w >> 5];
+            } else {
+                const uint32_t q = 4u * (w >> 5);
+                v = uint32_t(tabs->inv_sbox[q]) | (uint32_t(tabs->inv_sbox[q + 1]) << 8) |
+                    (uint32_t(tabs->inv_sbox[q + 2]) << 16) | (uint32_t(tabs->inv_sbox[q + 3]) << 24);
+            }
+            lds[L::si_offset / 4 + w] = v;
+        }
     }
 }
 
-// The four lookup addresses of one state word (byte t -> table t).
-struct WordAddr {
-    uint32_t a[4];
-};
-
-__device__ __forceinline__ WordAddr round_addr(uint32_t w, const LaneBases& lb, const uint32_t base[4])
+// Address of byte t of w in a table with entry stride 256 or 128.
+template <int STRIDE, int T>
+__device__ __forceinline__ uint32_t addr_of(uint32_t w, uint32_t m8, uint32_t m7, uint32_t base)
 {
-    WordAddr r;
-    r.a[0] = shl16_by8(w) | base[0];
-    r.a[1] = and_or(w, lb.m8, base[1]);
-    r.a[2] = and_or(w >> 8, lb.m8, base[2]);
-    r.a[3] = and_or(w >> 16, lb.m8, base[3]);
-    return r;
+    if (STRIDE == 256) {
+        if (T == 0) return shl16<8>(w) | base;
+        if (T == 1) return and_or(w, m8, base);
+        if (T == 2) return and_or(w >> 8, m8, base);
+        return and_or(w >> 16, m8, base);
+    } else {
+        if (T == 0) return and_or(shl16<7>(w), m7, base);
+        if (T == 1) return and_or(w >> 1, m7, base);
+        if (T == 2) return and_or(w >> 9, m7, base);
+        return and_or(w >> 17, m7, base);
+    }
+}
+
+// Address of byte t of w in the byte-packed InvS table.
+template <int T>
+__device__ __forceinline__ uint32_t packed_addr(uint32_t w, uint32_t m3, uint32_t m1f80, uint32_t base)
+{
+    const uint32_t x = T ? w >> (8 * T) : w;
+    return and_or(shl16<5>(x), m1f80, and_or(x, m3, base));
+}
+
+template <int PL>
+__device__ __forceinline__ void lookup4(uint32_t w, const uint32_t* lds, uint32_t m8, uint32_t m7,
+                                        const uint32_t base[4], uint32_t v[4])
+{
+    constexpr int S = PL == kPlace1 ? 128 : 256;
+    v[0] = lds_word(lds, addr_of<S, 0>(w, m8, m7, base[0]));
+    v[1] = lds_word(lds, addr_of<S, 1>(w, m8, m7, base[1]));
+    v[2] = lds_word(lds, addr_of<S, 2>(w, m8, m7, base[2]));
+    v[3] = lds_word(lds, addr_of<S, 3>(w, m8, m7, base[3]));
 }
 
 // One block through all rounds. K(i) returns round-key word i (uniform).
-template <int NR, bool kDecrypt, class K>
-__device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, const LaneBases& lb, const K& key)
+template <int NR, bool kDecrypt, int PL, class K>
+__device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
+                                             const K& key)
 {
+    constexpr int s = kDecrypt ? 3 : 1;  // neighbour column: j+1 (enc) or j-1 (dec), mod 4
     uint32_t w[4] = {in.x ^ key(0), in.y ^ key(1), in.z ^ key(2), in.w ^ key(3)};
 #pragma unroll
     for (int round = 1; round < NR; ++round) {
-        uint32_t v[4][4];  // v[t][j]: table t looked up with byte t of word j
+        uint32_t v[4][4];  // v[j][t]: lookup with byte t of word j
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            lookup4<PL>(w[j], lds, lb.m8, lb.m7, lb.b, v[j]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            WordAddr a = round_addr(w[j], lb, lb.b);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                v[t][j] = lds_word(lds, a.a[t]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int s = kDecrypt ? 3 : 1;  // j+1 (enc) or j-1 (dec), mod 4
-            uint32_t x = xor3(v[0][j], v[1][(j + s) & 3], v[2][(j + 2 * s) & 3]);
-            w[j] = xor3(x, v[3][(j + 3 * s) & 3], key(4 * round + j));
-        }
-    }
-    uint32_t f[4][4];
-    if (!kDecrypt) {
-        // byte t of the result row comes from table T_{t+2}, where byte t is {01}s
-        const uint32_t fb[4] = {lb.b[2], lb.b[3], lb.b[0], lb.b[1]};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            WordAddr a = round_addr(w[j], lb, fb);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                f[t][j] = lds_word(lds, a.a[t]);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            f[0][j] = lds_word(lds, and_or(shl16_by7(w[j]), lb.m7, lb.bs));
-            f[1][j] = lds_word(lds, and_or(w[j] >> 1, lb.m7, lb.bs));
-            f[2][j] = lds_word(lds, and_or(w[j] >> 9, lb.m7, lb.bs));
-            f[3][j] = lds_word(lds, and_or(w[j] >> 17, lb.m7, lb.bs));
+            const uint32_t a = v[j][0], b = v[(j + s) & 3][1], c = v[(j + 2 * s) & 3][2], d = v[(j + 3 * s) & 3][3];
+            const uint32_t k = key(4 * round + j);
+            if (PL == kPlace4) {
+                w[j] = xor3_key(xor3(a, b, c), d, k);
+            } else if (PL == kPlace2) {
+                // a: T0, c: T2 as stored; b, d need T1 = rotl8(T0), T3 = rotl8(T2)
+                w[j] = xor3_key(a, c, k) ^ rotl8(b ^ d);
+            } else {
+                // all from T0: a ^ rotl8(b) ^ rotl16(c) ^ rotl24(d)
+                w[j] = xor3_key(a, rotl8(b ^ rotl8(c ^ rotl8(d))), k);
+            }
         }
     }
     uint32_t o[4];
-    const int s = kDecrypt ? 3 : 1;
+    if (!kDecrypt) {
+        uint32_t f[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        uint32_t m = f[0][j] & 0xffu;
-        m = and_or(f[1][(j + s) & 3], lb.m8, m);
-        m = and_or(f[2][(j + 2 * s) & 3], lb.m16, m);
-        m = and_or(f[3][(j + 3 * s) & 3], lb.m24, m);
-        o[j] = m ^ key(4 * NR + j);
+        for (int j = 0; j < 4; ++j)
+            lookup4<PL>(w[j], lds, lb.m8, lb.m7, lb.f, f[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = f[j][0], b = f[(j + s) & 3][1], c = f[(j + 2 * s) & 3][2], d = f[(j + 3 * s) & 3][3];
+            uint32_t m;
+            if (PL == kPlace1) {
+                // T0 = ({02}s, s, s, {03}s): take s from byte 1 for rows 0 and 1, byte 2 for rows 2 and 3
+                m = (a >> 8) & 0xffu;
+                m = and_or(b, lb.m8, m);
+                m = and_or(c, lb.m16, m);
+                m = and_or(d << 8, lb.m24, m);
+            } else {
+                m = a & 0xffu;
+                m = and_or(b, lb.m8, m);
+                m = and_or(c, lb.m16, m);
+                m = and_or(d, lb.m24, m);
+            }
+            o[j] = m ^ key(4 * NR + j);
+        }
+    } else if (PL == kPlace4) {
+        uint32_t f[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t bs[4] = {lb.bs, lb.bs, lb.bs, lb.bs};
+            f[j][0] = lds_word(lds, addr_of<128, 0>(w[j], lb.m8, lb.m7, bs[0]));
+            f[j][1] = lds_word(lds, addr_of<128, 1>(w[j], lb.m8, lb.m7, bs[1]));
+            f[j][2] = lds_word(lds, addr_of<128, 2>(w[j], lb.m8, lb.m7, bs[2]));
+            f[j][3] = lds_word(lds, addr_of<128, 3>(w[j], lb.m8, lb.m7, bs[3]));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t m = f[j][0] & 0xffu;
+            m = and_or(f[(j + s) & 3][1], lb.m8, m);
+            m = and_or(f[(j + 2 * s) & 3][2], lb.m16, m);
+            m = and_or(f[(j + 3 * s) & 3][3], lb.m24, m);
+            o[j] = m ^ key(4 * NR + j);
+        }
+    } else {
+        uint32_t g[4][4];  // InvS bytes, zero-extended
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            g[j][0] = lds_byte(lds, packed_addr<0>(w[j], lb.m3, lb.m1f80, lb.bs));
+            g[j][1] = lds_byte(lds, packed_addr<1>(w[j], lb.m3, lb.m1f80, lb.bs));
+            g[j][2] = lds_byte(lds, packed_addr<2>(w[j], lb.m3, lb.m1f80, lb.bs));
+            g[j][3] = lds_byte(lds, packed_addr<3>(w[j], lb.m3, lb.m1f80, lb.bs));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t m = g[j][0] | (g[(j + s) & 3][1] << 8) | (g[(j + 2 * s) & 3][2] << 16) |
+                               (g[(j + 3 * s) & 3][3] << 24);
+            o[j] = m ^ key(4 * NR + j);
+        }
     }
     return make_uint4(o[0], o[1], o[2], o[3]);
 }

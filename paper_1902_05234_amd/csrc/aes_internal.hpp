@@ -14,11 +14,12 @@ struct RoundKeys {
 struct LaunchShape {
     int bpt;   // blocks per thread per iteration: 1, 2, 4
     int wg;    // workgroup size (multiple of 64, at most 1024)
-    int grid;  // number of workgroups
+    int grid;  // number of workgroups; 0 = persistent (CUs x workgroups that fit per CU)
 };
 
-hipError_t launch_ecb(const LaunchShape& shape, int nr, bool decrypt, const void* in, void* out, uint64_t nblocks,
-                      const RoundKeys& rk, hipStream_t stream);
+// placement: 0 = four tables, 1 = two tables, 2 = one table (aes_device.hpp)
+hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decrypt, const void* in, void* out,
+                      uint64_t nblocks, const RoundKeys& rk, int cus, hipStream_t stream);
 
 hipError_t launch_copy(const void* in, void* out, uint64_t n16, int grid, hipStream_t stream);
 

@@ -59,10 +59,11 @@ def test_ragged_sizes_all_key_sizes(oracle_lib, keybits, nblocks):
     assert_same(to_host(gpu_dec(ks, xd)), oracle_lib.ecb_decrypt(key, x), "dec %d-bit n=%d" % (keybits, nblocks))
 
 
-VARIANTS = [aes.Variant(bpt=b, wg=w, grid=g) for b in (1, 2, 4) for w in (64, 128, 256, 512, 1024) for g in (0, 3)]
+VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=g) for p in (0, 1, 2) for b in (1, 2, 4)
+            for w in (64, 128, 256, 512, 1024) for g in (0, 3)]
 
 
-@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: "bpt%d-wg%d-g%d" % (v.bpt, v.wg, v.grid))
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: "p%d-bpt%d-wg%d-g%d" % (v.placement, v.bpt, v.wg, v.grid))
 def test_every_variant(oracle_lib, variant):
     nblocks = 2 * 4096 + 77
     x = inputs.random_bytes(31, 16 * nblocks)

@@ -195,7 +195,7 @@ def test_ecb_argument_checks_before_any_device_call():
     assert lib.aes_ecb_encrypt(rk, 10, A, B + 8, 4, None) == aes.AES_EALIGN
     assert lib.aes_ecb_encrypt(rk, 10, A, A + 16, 4, None) == aes.AES_EINVAL  # partial overlap
     assert "overlap" in aes.aes_last_error()
-    bad = [aes.Variant(bpt=3), aes.Variant(wg=100), aes.Variant(wg=2048), aes.Variant(placement=7), aes.Variant(grid=-1)]
+    bad = [aes.Variant(bpt=3), aes.Variant(wg=100), aes.Variant(wg=2048), aes.Variant(placement=7), aes.Variant(placement=3), aes.Variant(grid=-1)]
     for v in bad:
         cv = v._c()
         assert lib.aes_ecb_crypt_variant(rk, 10, 0, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
