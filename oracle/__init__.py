@@ -52,6 +52,9 @@ class Oracle:
             f = getattr(lib, name)
             f.argtypes = [_p8, ctypes.c_int, _p8, _p8, ctypes.c_uint64, ctypes.c_int]
             f.restype = ctypes.c_int
+        lib.oracle_ctr_crypt.argtypes = [_p8, ctypes.c_int, _p8, ctypes.c_uint64, _p8, _p8, ctypes.c_uint64,
+                                         ctypes.c_int]
+        lib.oracle_ctr_crypt.restype = ctypes.c_int
 
     # -- field ------------------------------------------------------------
     def xtime(self, a: int) -> int:
@@ -137,6 +140,23 @@ class Oracle:
 
     def ecb_decrypt(self, key: bytes, data, nthreads: int | None = None) -> np.ndarray:
         return self._ecb("oracle_ecb_decrypt", key, data, nthreads)
+
+    def ctr_crypt(self, key: bytes, iv: bytes, data, offset: int = 0, nthreads: int | None = None) -> np.ndarray:
+        """AES CTR of any number of bytes (encryption and decryption are the
+        same); data block j uses counter iv + offset + j, 128-bit big-endian."""
+        key, iv = bytes(key), bytes(iv)
+        if len(iv) != 16:
+            raise ValueError("the counter block is 16 bytes")
+        src = np.ascontiguousarray(np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray, memoryview)) else data, dtype=np.uint8).reshape(-1)
+        out = np.empty_like(src)
+        k = np.frombuffer(key, dtype=np.uint8).copy()
+        c = np.frombuffer(iv, dtype=np.uint8).copy()
+        nthreads = nthreads or (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+        rc = self._lib.oracle_ctr_crypt(_ptr(k), 8 * len(key), _ptr(c), int(offset) & (2**64 - 1), _ptr(src),
+                                        _ptr(out), src.size, int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle rejected the key (%d bytes)" % len(key))
+        return out
 
 
 _default = None

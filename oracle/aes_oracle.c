@@ -399,6 +399,103 @@ static int ecb(const uint8_t *key, int keybits, const uint8_t *in, uint8_t *out,
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------- CTR driver
+ *
+ * Counter mode (section 3.1.5, eq 5): block i of the output is block i of
+ * the input XOR the cipher of a counter block, and counter blocks of
+ * successive data blocks are successive integers.  Reading of the paper's
+ * counter (its range for R is garbled): the counter block is one 128-bit
+ * big-endian integer, data block j (counted from 0) uses iv + offset + j
+ * modulo 2^128, so the paper's R is iv + offset - 1.  A partial last block
+ * uses the leading bytes of its key-stream block.  Decryption is the same
+ * operation.
+ */
+
+/* out = c + add (mod 2^128), both big-endian, one byte at a time */
+static void counter_add(const uint8_t c[16], uint64_t add, uint8_t out[16])
+{
+    unsigned carry = 0;
+    for (int i = 15; i >= 0; --i) {
+        unsigned v = (unsigned)c[i] + (unsigned)(add & 0xffu) + carry;
+        out[i] = (uint8_t)(v & 0xffu);
+        carry = v >> 8;
+        add >>= 8;
+    }
+}
+
+typedef struct {
+    const uint8_t *w;
+    int nr;
+    const uint8_t *ctr0; /* counter of data block 0 */
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t nbytes;
+    uint64_t first, count; /* block range */
+} ctr_job;
+
+static void *ctr_worker(void *arg)
+{
+    const ctr_job *j = (const ctr_job *)arg;
+    const uint64_t end = j->first + j->count;
+    for (uint64_t b = j->first; b < end; ++b) {
+        uint8_t ctr[16], ks[16];
+        counter_add(j->ctr0, b, ctr);
+        cipher_block(j->w, j->nr, ctr, ks);
+        uint64_t n = j->nbytes - 16 * b;
+        if (n > 16)
+            n = 16;
+        for (uint64_t k = 0; k < n; ++k)
+            j->out[16 * b + k] = (uint8_t)(j->in[16 * b + k] ^ ks[k]);
+    }
+    return NULL;
+}
+
+static int ctr(const uint8_t *key, int keybits, const uint8_t iv[16], uint64_t offset, const uint8_t *in,
+               uint8_t *out, uint64_t nbytes, int nthreads)
+{
+    uint8_t w[16 * 15], ctr0[16];
+    int nr;
+    if (expand_key(key, keybits, w, &nr) != ORACLE_OK || iv == NULL)
+        return ORACLE_EINVAL;
+    if (nbytes == 0)
+        return ORACLE_OK;
+    if (in == NULL || out == NULL)
+        return ORACLE_EINVAL;
+    counter_add(iv, offset, ctr0);
+    uint64_t nblocks = (nbytes + 15) / 16;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((uint64_t)nthreads > nblocks)
+        nthreads = (int)nblocks;
+    ctr_job *jobs = (ctr_job *)calloc((size_t)nthreads, sizeof(ctr_job));
+    pthread_t *tid = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tid) {
+        free(jobs);
+        free(tid);
+        return ORACLE_EINVAL;
+    }
+    uint64_t per = nblocks / (uint64_t)nthreads, extra = nblocks % (uint64_t)nthreads, next = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        uint64_t cnt = per + ((uint64_t)t < extra ? 1 : 0);
+        jobs[t] = (ctr_job){w, nr, ctr0, in, out, nbytes, next, cnt};
+        next += cnt;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tid[t], NULL, ctr_worker, &jobs[t]) != 0)
+            break;
+        started = t;
+    }
+    ctr_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tid[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t)
+        ctr_worker(&jobs[t]);
+    free(jobs);
+    free(tid);
+    return ORACLE_OK;
+}
+
 /* ---------------------------------------------------------- exported API */
 
 uint8_t oracle_xtime(uint8_t a) { return gf_xtime(a); }
@@ -474,4 +571,12 @@ int oracle_ecb_decrypt(const uint8_t *key, int keybits, const uint8_t *in, uint8
                        uint64_t nblocks, int nthreads)
 {
     return ecb(key, keybits, in, out, nblocks, nthreads, 1);
+}
+
+/* CTR encryption or decryption of nbytes (any length); counter of data
+ * block j is iv + offset + j (128-bit big-endian, mod 2^128). */
+int oracle_ctr_crypt(const uint8_t *key, int keybits, const uint8_t iv[16], uint64_t offset,
+                     const uint8_t *in, uint8_t *out, uint64_t nbytes, int nthreads)
+{
+    return ctr(key, keybits, iv, offset, in, out, nbytes, nthreads);
 }

@@ -60,6 +60,20 @@ def openssl_ecb(key: bytes, data: bytes, decrypt: bool) -> bytes:
     return r.stdout
 
 
+def openssl_ctr(key: bytes, iv: bytes, data: bytes) -> bytes:
+    """AES-CTR through the OpenSSL command-line tool (128-bit big-endian counter)."""
+    cmd = ["openssl", "enc", "-aes-%d-ctr" % (8 * len(key)), "-K", key.hex(), "-iv", iv.hex()]
+    r = subprocess.run(cmd, input=data, capture_output=True, check=True)
+    return r.stdout
+
+
+def counter_blocks(iv: bytes, offset: int, n: int) -> np.ndarray:
+    """n successive 128-bit big-endian counters from iv + offset, by Python integers."""
+    c0 = int.from_bytes(iv, "big") + offset
+    out = b"".join(((c0 + j) % (1 << 128)).to_bytes(16, "big") for j in range(n))
+    return np.frombuffer(out, dtype=np.uint8).copy()
+
+
 # ---------------------------------------------------------------- the pins
 def pin_paper_field_examples(o):
     """Section 3.2.1 worked examples (Defs. 1-3, eqs 7-17)."""
@@ -261,6 +275,58 @@ def pin_ecb_structure(o):
     assert np.array_equal(yp, y[perm])
 
 
+# counters whose increments carry within the low half, across the two 64-bit
+# halves, and wrap at 2^128
+CTR_EDGE_IVS = [
+    bytes(15) + b"\xfe",
+    bytes(8) + b"\xff" * 8,
+    bytes(7) + b"\x05" + b"\xff" * 8,
+    b"\xff" * 16,
+]
+
+
+def pin_ctr_openssl(o):
+    """CTR (section 3.1.5, eq 5) against the OpenSSL command-line tool: all
+    key sizes, seeded keys and counters, lengths with a partial last block,
+    and counters that carry across the 64-bit halves or wrap at 2^128."""
+    if not openssl_available():
+        raise AssertionError("openssl command-line tool not found")
+    for keybits in (128, 192, 256):
+        key = inputs.random_key(3000 + keybits, keybits)
+        ivs = [inputs.random_bytes(3100 + keybits, 16).tobytes()] + CTR_EDGE_IVS
+        for i, iv in enumerate(ivs):
+            for n in (1, 15, 16, 17, 16 * 37 + 5):
+                data = inputs.random_bytes(3200 + 7 * i + n, n).tobytes()
+                assert o.ctr_crypt(key, iv, data).tobytes() == openssl_ctr(key, iv, data), (keybits, iv.hex(), n)
+
+
+def pin_ctr_structure(o):
+    """CTR (eq 5): the key stream is the cipher of successive counters and does
+    not depend on the data; applying it twice restores the data; a start
+    offset of k blocks continues the same stream; a prefix of the data gets
+    the prefix of the result; the thread count is irrelevant."""
+    for keybits in (128, 192, 256):
+        key = inputs.random_key(3300 + keybits, keybits)
+        for iv in [inputs.random_bytes(3301, 16).tobytes()] + CTR_EDGE_IVS:
+            nblk = 19
+            zeros = np.zeros(16 * nblk, dtype=np.uint8)
+            stream = o.ctr_crypt(key, iv, zeros, nthreads=3)
+            assert np.array_equal(stream, o.ecb_encrypt(key, counter_blocks(iv, 0, nblk))), iv.hex()
+            stream7 = o.ctr_crypt(key, iv, zeros[: 16 * (nblk - 7)], offset=7, nthreads=2)
+            assert np.array_equal(stream7, stream[16 * 7:]), iv.hex()
+            x = inputs.random_bytes(3302 + keybits, 16 * nblk - 9)
+            y = o.ctr_crypt(key, iv, x, nthreads=1)
+            assert np.array_equal(y ^ x, stream[: x.size])
+            assert np.array_equal(o.ctr_crypt(key, iv, y, nthreads=4), x)
+            assert np.array_equal(o.ctr_crypt(key, iv, x[:33]), y[:33])
+    # a start offset past 2^64 blocks still adds as a 128-bit integer
+    key = inputs.random_key(3400, 128)
+    iv = b"\x00" * 7 + b"\x01" + b"\xff" * 8
+    off = (1 << 64) - 3
+    got = o.ctr_crypt(key, iv, np.zeros(16 * 6, dtype=np.uint8), offset=off)
+    assert np.array_equal(got, o.ecb_encrypt(key, counter_blocks(iv, off, 6)))
+
+
 ALL_PINS = [
     pin_paper_field_examples,
     pin_field_matches_polynomial_arithmetic,
@@ -273,4 +339,9 @@ ALL_PINS = [
     pin_round_trip,
     pin_ecb_structure,
     pin_openssl_known_answers,
+    pin_ctr_structure,
+    pin_ctr_openssl,
 ]
+
+# pins that need the openssl command-line tool
+OPENSSL_PINS = (pin_openssl_known_answers, pin_ctr_openssl)
