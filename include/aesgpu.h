@@ -73,8 +73,8 @@ int aes_expand_key(const uint8_t *key, int keybits, uint32_t *rk_enc, uint32_t *
  *   in, out: device pointers, 16-byte aligned, nblocks*16 bytes each.
  *            in == out (in place) is allowed; any other overlap is AES_EINVAL.
  *   nblocks: number of 16-byte blocks; 0 is a no-op returning AES_OK.
- * The kernel variant comes from the tuning table (aes_tune_set), default
- * 16 bytes per thread, 1024-thread workgroups, four replicated LDS T-tables.
+ * The kernel variant comes from the tuning table (aes_tune_get/aes_tune_set),
+ * one entry per key size, direction and size bucket.
  */
 int aes_ecb_encrypt(const uint32_t *rk, int nr, const void *in, void *out, size_t nblocks, void *stream);
 int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_t nblocks, void *stream);
@@ -103,6 +103,33 @@ int aes_ecb_crypt_variant(const uint32_t *rk, int nr, int decrypt, const void *i
 int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant *v);
 int aes_tune_get(int nr, int decrypt, size_t nblocks, aes_variant *v);
 int aes_size_bucket(size_t nblocks);
+
+/*
+ * aes_ctr_crypt -- counter mode (section 3.1.5, eq 5; parallel per Table 1):
+ * output byte k of data block j is input byte k XOR byte k of
+ * cipher(counter c0 + j), counters being 128-bit big-endian integers taken
+ * modulo 2^128.  Encryption and decryption are the same call.
+ *   rk:           host pointer to the ENCRYPTION schedule (rk_enc) of
+ *                 aes_expand_key, 4*(nr+1) words, copied into the launch.
+ *   nr:           10, 12 or 14.
+ *   iv:           host pointer to the 16-byte initial counter block.
+ *   block_offset: c0 = iv + block_offset (a 128-bit addition), so a long
+ *                 message can be processed in pieces: a piece starting at
+ *                 byte 16*k of the message passes block_offset = k.  The
+ *                 paper's R (counter of block i = R + i, i from 1) is
+ *                 c0 - 1.
+ *   in, out:      device pointers, 16-byte aligned, nbytes each; in == out
+ *                 is allowed, any other overlap is AES_EINVAL.
+ *   nbytes:       any length; a partial last block uses the leading bytes
+ *                 of its key-stream block.  0 is a no-op returning AES_OK.
+ * The variant is the encryption entry of the tuning table for
+ * ceil(nbytes/16) blocks.  Asynchronous on stream.
+ */
+int aes_ctr_crypt(const uint32_t *rk, int nr, const uint8_t *iv, uint64_t block_offset, const void *in, void *out,
+                  size_t nbytes, void *stream);
+/* Same with an explicit variant (AES_EINVAL outside the search space). */
+int aes_ctr_crypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, uint64_t block_offset, const void *in,
+                          void *out, size_t nbytes, const aes_variant *variant, void *stream);
 
 /*
  * Batched ECB: many independent messages, each with its own key, key size
@@ -173,6 +200,84 @@ typedef struct {
 int aes_ecb_batch(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, const uint32_t *key_table_dev,
                   size_t n_slots, const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
                   uint32_t *counters_dev, const aes_batch_config *cfg, void *stream);
+
+/*
+ * Serving: a native continuous-batching engine over aes_ecb_batch (not in the
+ * paper).  Requests read blocks of one device input pool and get their
+ * output placed in a device output arena by the engine.  A worker thread
+ * admits requests in arrival order while the device budget (input + output
+ * bytes of admitted, unfinished requests) and the arena allow, and whenever
+ * one of nslots stream slots is free it runs everything admitted so far as
+ * one batched launch; requests arriving meanwhile join the next batch, and
+ * batches on different slots overlap on the device.
+ *
+ * Memory: the caller provides every buffer: key table, input pool, output
+ * arena, a device workspace of aes_server_workspace_bytes(cfg) bytes (work
+ * lists and counters) and pinned host staging of aes_server_staging_bytes(cfg)
+ * bytes (e.g. hipHostMalloc).  The engine creates nslots streams and events
+ * on the current device.  All of them must outlive the server.
+ */
+typedef struct {
+    uint64_t in_block;  /* first block of the request in the input pool */
+    uint64_t nblocks;   /* > 0 */
+    uint32_t key_slot;  /* index into the key table */
+    uint32_t decrypt;   /* 0 = encrypt, nonzero = decrypt */
+} aes_request;
+
+#define AES_SERVED_DONE 0
+#define AES_SERVED_REJECTED 1 /* can never run: empty, over budget/arena, bad slot, outside the pool */
+#define AES_SERVED_FAILED 2   /* its batch failed to launch or run */
+typedef struct {
+    uint64_t id;          /* submission order, from 0 */
+    double arrival_s;     /* seconds on the server's clock (replay: scheduled arrival) */
+    double admitted_s;
+    double done_s;        /* when the engine saw the batch complete */
+    uint64_t out_block;   /* output position in the arena (valid when DONE) */
+    uint64_t nblocks;
+    int32_t status;       /* AES_SERVED_* */
+    int32_t batch;        /* index of the batch that ran the request */
+} aes_served;
+
+typedef struct {
+    uint64_t budget_bytes;     /* cap on input + output bytes of admitted, unfinished requests */
+    uint32_t chunk_blocks;     /* work-item size */
+    uint32_t max_batch_items;  /* work items per batch (sizes the workspace) */
+    int32_t nslots;            /* batches in flight, 1..16 (one stream each) */
+    int32_t bpt, wg, grid;     /* batch kernel shape (grid 0 = one workgroup per CU) */
+    int32_t auto_release;      /* nonzero: output space is freed when a request completes */
+    int32_t dry_run;           /* nonzero: no device work; batches complete after dry_run_seconds */
+    double dry_run_seconds;
+} aes_serve_config;
+
+typedef struct {
+    uint64_t batches;
+    uint64_t max_device_bytes_in_use;
+    uint64_t arena_blocks_in_use;
+    uint64_t pending;
+} aes_serve_stats;
+
+typedef struct aes_server aes_server;
+
+size_t aes_server_workspace_bytes(const aes_serve_config *cfg);
+size_t aes_server_staging_bytes(const aes_serve_config *cfg);
+/* AES_EINVAL bad config or null buffer; AES_ERANGE workspace/staging too small;
+ * AES_EHIP stream/event creation failed. */
+int aes_server_create(const aes_serve_config *cfg, const uint32_t *key_table_dev, size_t n_slots, const void *in_pool,
+                      size_t in_blocks, void *out_arena, size_t out_blocks, void *workspace_dev,
+                      size_t workspace_bytes, void *staging_host, size_t staging_bytes, aes_server **out);
+/* Thread-safe; requests get consecutive ids starting at *first_id. */
+int aes_server_submit(aes_server *s, const aes_request *reqs, size_t n, uint64_t *first_id);
+/* Moves up to cap finished requests (any order of ids) into out; *n = count. */
+int aes_server_poll(aes_server *s, aes_served *out, size_t cap, size_t *n);
+/* Frees the output space of finished requests (no-op with auto_release). */
+int aes_server_release(aes_server *s, const aes_served *done, size_t n);
+int aes_server_stats(aes_server *s, aes_serve_stats *stats);
+/* Finishes every submitted request, then frees the engine (not the buffers). */
+int aes_server_destroy(aes_server *s);
+/* Open-loop replay on an auto_release server: request i is submitted at
+ * arrival_s[i] seconds after the call starts; returns when all have finished,
+ * with results[i] for request i (arrival_s = scheduled arrival). */
+int aes_serve_replay(aes_server *s, const aes_request *reqs, const double *arrival_s, size_t n, aes_served *results);
 
 /* Host copies of the library's source tables (for inspection and tests):
  * sbox/inv_sbox 256 bytes each; te0/td0 256 column words each (eqs 22 and

@@ -87,6 +87,9 @@ def _lib() -> ctypes.CDLL:
                 "aes_ecb_encrypt": ([_u32p, _c_i, _c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_ecb_decrypt": ([_u32p, _c_i, _c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_ecb_crypt_variant": ([_u32p, _c_i, _c_i, _c_p, _c_p, _c_sz, ctypes.POINTER(_Variant), _c_p], _c_i),
+                "aes_ctr_crypt": ([_u32p, _c_i, _u8p, ctypes.c_uint64, _c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_ctr_crypt_variant": ([_u32p, _c_i, _u8p, ctypes.c_uint64, _c_p, _c_p, _c_sz,
+                                           ctypes.POINTER(_Variant), _c_p], _c_i),
                 "aes_tune_set": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_tune_get": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_size_bucket": ([_c_sz], _c_i),
@@ -107,8 +110,10 @@ def _lib() -> ctypes.CDLL:
 def exported_symbols():
     """Names this binding expects the library to export."""
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
-            "aes_ecb_crypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
-            "aes_ecb_batch", "aes_device_copy", "aes_host_tables"]
+            "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
+            "aes_ecb_batch", "aes_device_copy", "aes_host_tables", "aes_server_workspace_bytes",
+            "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
+            "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay"]
 
 
 def aes_last_error() -> str:
@@ -127,6 +132,17 @@ def _stream_handle(stream) -> int:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def _bytes_of(t, name: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.numel() * t.element_size()
 
 
 def _blocks_of(t, name: str) -> int:
@@ -211,6 +227,34 @@ def aes_ecb_crypt_variant(rk, nr: int, decrypt: bool, inp, out, variant: Variant
     return _crypt(fn, rk, nr, inp, out, nblocks, stream)
 
 
+# ------------------------------------------------------------------ CTR mode
+def _ctr(fn, rk, nr, iv, block_offset, inp, out, nbytes, stream, *extra):
+    n_in, n_out = _bytes_of(inp, "in"), _bytes_of(out, "out")
+    nbytes = n_in if nbytes is None else int(nbytes)
+    if nbytes < 0 or nbytes > n_in or nbytes > n_out:
+        raise ValueError("nbytes=%d exceeds a buffer (in %d, out %d bytes)" % (nbytes, n_in, n_out))
+    iv = bytes(iv)
+    if len(iv) != 16:
+        raise ValueError("the counter block is 16 bytes, got %d" % len(iv))
+    rk = _u32_array(rk, 4 * (int(nr) + 1))
+    ivb = (ctypes.c_uint8 * 16).from_buffer_copy(iv)
+    _check(fn(rk.ctypes.data_as(_u32p), int(nr), ivb, int(block_offset) & (2**64 - 1), inp.data_ptr(),
+              out.data_ptr(), nbytes, *extra, _stream_handle(stream)))
+    return out
+
+
+def aes_ctr_crypt(rk, nr: int, iv: bytes, block_offset: int, inp, out, nbytes: int | None = None, stream=None):
+    """CTR encryption/decryption of nbytes (default: all of ``inp``); rk is
+    the encryption schedule; data block j uses counter iv + block_offset + j."""
+    return _ctr(_lib().aes_ctr_crypt, rk, nr, iv, block_offset, inp, out, nbytes, stream)
+
+
+def aes_ctr_crypt_variant(rk, nr: int, iv: bytes, block_offset: int, inp, out, variant: Variant,
+                          nbytes: int | None = None, stream=None):
+    v = variant._c()
+    return _ctr(_lib().aes_ctr_crypt_variant, rk, nr, iv, block_offset, inp, out, nbytes, stream, ctypes.byref(v))
+
+
 def aes_tune_set(nr: int, decrypt: bool, nblocks: int, variant: Variant):
     v = variant._c()
     _check(_lib().aes_tune_set(int(nr), int(bool(decrypt)), int(nblocks), ctypes.byref(v)))
@@ -237,6 +281,13 @@ def ecb_decrypt(ks: KeySchedule, x, out=None, stream=None):
     import torch
     out = torch.empty_like(x) if out is None else out
     return aes_ecb_decrypt(ks.rk_dec, ks.nr, x, out, stream=stream)
+
+
+def ctr_crypt(ks: KeySchedule, iv: bytes, x, out=None, block_offset: int = 0, stream=None):
+    """CTR over a uint8 CUDA tensor of any length; returns ``out``."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    return aes_ctr_crypt(ks.rk_enc, ks.nr, iv, block_offset, x, out, stream=stream)
 
 
 # ---------------------------------------------------------------- batched ECB
@@ -295,3 +346,138 @@ def aes_host_tables():
     _check(_lib().aes_host_tables(sbox.ctypes.data_as(_u8p), inv.ctypes.data_as(_u8p), te0.ctypes.data_as(_u32p),
                                   td0.ctypes.data_as(_u32p)))
     return sbox, inv, te0, td0
+
+
+# -------------------------------------------------------------- native serving
+REQUEST_DTYPE = np.dtype([("in_block", "<u8"), ("nblocks", "<u8"), ("key_slot", "<u4"), ("decrypt", "<u4")])
+SERVED_DTYPE = np.dtype([("id", "<u8"), ("arrival_s", "<f8"), ("admitted_s", "<f8"), ("done_s", "<f8"),
+                         ("out_block", "<u8"), ("nblocks", "<u8"), ("status", "<i4"), ("batch", "<i4")])
+assert REQUEST_DTYPE.itemsize == 24 and SERVED_DTYPE.itemsize == 56
+AES_SERVED_DONE, AES_SERVED_REJECTED, AES_SERVED_FAILED = 0, 1, 2
+
+
+class _ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("chunk_blocks", ctypes.c_uint32),
+                ("max_batch_items", ctypes.c_uint32), ("nslots", ctypes.c_int32), ("bpt", ctypes.c_int32),
+                ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("auto_release", ctypes.c_int32),
+                ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double)]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("max_device_bytes_in_use", ctypes.c_uint64),
+                ("arena_blocks_in_use", ctypes.c_uint64), ("pending", ctypes.c_uint64)]
+
+
+def _serve_sigs(lib):
+    if getattr(lib, "_serve_sigs", False):
+        return
+    cfgp = ctypes.POINTER(_ServeConfig)
+    lib.aes_server_workspace_bytes.argtypes = [cfgp]
+    lib.aes_server_workspace_bytes.restype = _c_sz
+    lib.aes_server_staging_bytes.argtypes = [cfgp]
+    lib.aes_server_staging_bytes.restype = _c_sz
+    lib.aes_server_create.argtypes = [cfgp, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz,
+                                      ctypes.POINTER(_c_p)]
+    lib.aes_server_create.restype = _c_i
+    lib.aes_server_submit.argtypes = [_c_p, _c_p, _c_sz, ctypes.POINTER(ctypes.c_uint64)]
+    lib.aes_server_submit.restype = _c_i
+    lib.aes_server_poll.argtypes = [_c_p, _c_p, _c_sz, ctypes.POINTER(_c_sz)]
+    lib.aes_server_poll.restype = _c_i
+    lib.aes_server_release.argtypes = [_c_p, _c_p, _c_sz]
+    lib.aes_server_release.restype = _c_i
+    lib.aes_server_stats.argtypes = [_c_p, ctypes.POINTER(_ServeStats)]
+    lib.aes_server_stats.restype = _c_i
+    lib.aes_server_destroy.argtypes = [_c_p]
+    lib.aes_server_destroy.restype = _c_i
+    lib.aes_serve_replay.argtypes = [_c_p, _c_p, _c_p, _c_sz, _c_p]
+    lib.aes_serve_replay.restype = _c_i
+    lib._serve_sigs = True
+
+
+class Server:
+    """The native continuous-batching engine (aes_server_* in aesgpu.h).
+
+    Device buffers are torch tensors owned by the caller (kept alive here);
+    the work-list workspace and pinned staging are allocated here with torch.
+    ``dry_run`` runs the admission policy with no device work (CPU only).
+    """
+
+    def __init__(self, key_table_dev=None, in_pool=None, out_arena=None, *, n_slots=None, in_blocks=None,
+                 out_blocks=None, budget_bytes=32 << 30, chunk_blocks=1024, max_batch_items=1 << 18, nslots=4,
+                 bpt=1, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0):
+        lib = _lib()
+        _serve_sigs(lib)
+        self._lib = lib
+        self.cfg = _ServeConfig(int(budget_bytes), int(chunk_blocks), int(max_batch_items), int(nslots), int(bpt),
+                                int(wg), int(grid), int(bool(auto_release)), int(bool(dry_run)), float(dry_run_seconds))
+        ws = lib.aes_server_workspace_bytes(ctypes.byref(self.cfg))
+        st = lib.aes_server_staging_bytes(ctypes.byref(self.cfg))
+        self._keep = [key_table_dev, in_pool, out_arena]
+        if dry_run:
+            self._ws = np.zeros(max(ws, 1), dtype=np.uint8)
+            self._st = np.zeros(max(st, 1), dtype=np.uint8)
+            ws_ptr, st_ptr = self._ws.ctypes.data, self._st.ctypes.data
+        else:
+            import torch
+            self._ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
+            self._st = torch.empty(st, dtype=torch.uint8, pin_memory=True)
+            ws_ptr, st_ptr = self._ws.data_ptr(), self._st.data_ptr()
+            torch.cuda.synchronize()
+
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+
+        n_slots = n_slots if n_slots is not None else key_table_dev.numel() // AES_KEY_SLOT_WORDS
+        in_blocks = in_blocks if in_blocks is not None else in_pool.numel() // 16
+        out_blocks = out_blocks if out_blocks is not None else out_arena.numel() // 16
+        self.out_blocks = out_blocks
+        h = _c_p()
+        _check_rc(lib.aes_server_create(ctypes.byref(self.cfg), ptr(key_table_dev), n_slots, ptr(in_pool), in_blocks,
+                                        ptr(out_arena), out_blocks, ws_ptr, ws, st_ptr, st, ctypes.byref(h)),
+                  "aes_server_create")
+        self._h = h
+
+    def submit(self, reqs) -> int:
+        reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        first = ctypes.c_uint64(0)
+        _check_rc(self._lib.aes_server_submit(self._h, reqs.ctypes.data if reqs.size else None, reqs.size,
+                                              ctypes.byref(first)), "aes_server_submit")
+        return first.value
+
+    def poll(self, cap: int = 4096) -> np.ndarray:
+        out = np.zeros(cap, dtype=SERVED_DTYPE)
+        n = ctypes.c_size_t(0)
+        _check_rc(self._lib.aes_server_poll(self._h, out.ctypes.data, cap, ctypes.byref(n)), "aes_server_poll")
+        return out[:n.value]
+
+    def release(self, served: np.ndarray):
+        served = np.ascontiguousarray(served, dtype=SERVED_DTYPE)
+        _check_rc(self._lib.aes_server_release(self._h, served.ctypes.data if served.size else None, served.size),
+                  "aes_server_release")
+
+    def stats(self) -> dict:
+        s = _ServeStats()
+        _check_rc(self._lib.aes_server_stats(self._h, ctypes.byref(s)), "aes_server_stats")
+        return {"batches": s.batches, "max_device_bytes_in_use": s.max_device_bytes_in_use,
+                "arena_blocks_in_use": s.arena_blocks_in_use, "pending": s.pending}
+
+    def replay(self, reqs, arrival_s) -> np.ndarray:
+        reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        out = np.zeros(reqs.size, dtype=SERVED_DTYPE)
+        _check_rc(self._lib.aes_serve_replay(self._h, reqs.ctypes.data, arr.ctypes.data, reqs.size,
+                                             out.ctypes.data), "aes_serve_replay")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.aes_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _check_rc(rc: int, what: str):
+    if rc != AES_OK:
+        raise AesError(rc, "%s failed (%s)" % (what, aes_last_error() or "see argument checks"))

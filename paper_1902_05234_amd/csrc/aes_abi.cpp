@@ -174,6 +174,47 @@ int run_ecb(const uint32_t* rk, int nr, bool decrypt, const void* in, void* out,
     return AES_OK;
 }
 
+int run_ctr(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset, const void* in, void* out,
+            size_t nbytes, const aes_variant* v, void* stream)
+{
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (rk == nullptr || iv == nullptr)
+        return fail(AES_EINVAL, "null round-key or counter pointer");
+    if (nbytes == 0)
+        return AES_OK;
+    if (in == nullptr || out == nullptr)
+        return fail(AES_EINVAL, "null buffer pointer with nbytes=%zu", nbytes);
+    if (nbytes > (SIZE_MAX >> 1))
+        return fail(AES_EINVAL, "nbytes=%zu too large", nbytes);
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u)
+        return fail(AES_EALIGN, "in/out must be 16-byte aligned");
+    if (ranges_partially_overlap(in, out, (uint64_t)nbytes))
+        return fail(AES_EINVAL, "in and out overlap without being the same buffer");
+    int rc = check_variant(v);
+    if (rc != AES_OK)
+        return rc;
+    // c0 = iv + block_offset as a 128-bit big-endian sum
+    Counter128 c0{0, 0};
+    for (int i = 0; i < 8; ++i) {
+        c0.hi = (c0.hi << 8) | iv[i];
+        c0.lo = (c0.lo << 8) | iv[8 + i];
+    }
+    const uint64_t lo = c0.lo + block_offset;
+    c0.hi += lo < c0.lo ? 1u : 0u;
+    c0.lo = lo;
+    RoundKeys keys{};
+    std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    LaunchShape shape{v->bpt, v->wg, v->grid};
+    hipError_t e = launch_ctr(shape, v->placement, nr, in, out, nbytes, c0, keys, cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "CTR kernel launch");
+    return AES_OK;
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -281,6 +322,24 @@ int aes_ecb_crypt_variant(const uint32_t* rk, int nr, int decrypt, const void* i
     return run_ecb(rk, nr, decrypt != 0, in, out, nblocks, variant, stream);
 }
 
+int aes_ctr_crypt(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset, const void* in, void* out,
+                  size_t nbytes, void* stream)
+{
+    aes_variant v;
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    aes_tune_get(nr, 0, (nbytes + 15u) / 16u, &v);
+    return run_ctr(rk, nr, iv, block_offset, in, out, nbytes, &v, stream);
+}
+
+int aes_ctr_crypt_variant(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset, const void* in,
+                          void* out, size_t nbytes, const aes_variant* variant, void* stream)
+{
+    if (variant == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    return run_ctr(rk, nr, iv, block_offset, in, out, nbytes, variant, stream);
+}
+
 int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant* v)
 {
     if (!valid_nr(nr))
@@ -377,14 +436,10 @@ int aes_ecb_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, co
     int cus = device_cu_count();
     if (cus <= 0)
         return fail(AES_EHIP, "cannot query the current HIP device");
-    int grid = c.grid > 0 ? c.grid : cus;
-    int enc_groups = c.enc_groups;
-    if (enc_groups < 0 || enc_groups > grid)
-        enc_groups = (int)((uint64_t)grid * n_enc / (n_enc + n_dec));
-    if (n_enc > 0 && enc_groups == 0)
-        enc_groups = 1;
-    if (n_dec > 0 && enc_groups == grid && grid > 1)
-        enc_groups = grid - 1;
+    int grid = 0, enc_groups = 0;
+    // the item counts stand in for the byte shares (the items live on the device)
+    batch_grid(n_enc, n_dec, n_enc, n_enc + n_dec, c.wg, c.grid > 0 ? c.grid : cus, c.enc_groups, &grid,
+               &enc_groups);
     BatchArgs a{reinterpret_cast<const WorkItem*>(items_dev), (uint32_t)n_enc, (uint32_t)n_dec, key_table_dev,
                 (uint32_t)n_slots, in_base, out_base, (uint64_t)in_blocks, (uint64_t)out_blocks, counters_dev,
                 (uint32_t)enc_groups};

@@ -16,6 +16,7 @@
 // Every item is checked against the arena sizes and the key-table size
 // before use; a bad item is skipped and counted in counters[3].
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 
 #include "aes_device.hpp"
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict_
     __shared__ uint32_t lds[Layout<kPlace4, true>::words];
     bool dec = blockIdx.x >= enc_groups;
     for (int pass = 0; pass < 2; ++pass, dec = !dec) {
+        if ((dec ? n_dec : n_enc) == 0)
+            continue;  // uniform across the grid: no tables to load, no barrier to meet
         if (dec)
             fill_tables<kPlace4, true>(lds, &c_tables);
         else
@@ -133,6 +136,33 @@ __global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict_
             __threadfence();
         }
     }
+}
+
+void batch_grid(uint64_t n_enc, uint64_t n_dec, uint64_t enc_blocks, uint64_t total_blocks, int wg, int max_grid,
+                int requested_enc_groups, int* grid, int* enc_groups)
+{
+    // one wave claims one item at a time: no point in more workgroups than
+    // (items / waves per workgroup) per direction
+    const uint64_t wpw = (uint64_t)(wg / 64);
+    const uint64_t need_e = (n_enc + wpw - 1) / wpw, need_d = (n_dec + wpw - 1) / wpw;
+    uint64_t g = std::min<uint64_t>((uint64_t)max_grid, std::max<uint64_t>(1, need_e + need_d));
+    if (n_enc && n_dec && g < 2)
+        g = 2;
+    int64_t e;
+    if (n_enc == 0)
+        e = 0;
+    else if (n_dec == 0)
+        e = (int64_t)g;
+    else if (requested_enc_groups >= 0)
+        e = requested_enc_groups;
+    else
+        e = (int64_t)((g * enc_blocks + total_blocks / 2) / std::max<uint64_t>(1, total_blocks));
+    if (n_enc && e < 1)
+        e = 1;
+    if (n_dec && e > (int64_t)g - 1)
+        e = (int64_t)g - 1;
+    *grid = (int)g;
+    *enc_groups = (int)e;
 }
 
 hipError_t launch_batch(const BatchArgs& a, int bpt, int grid, int wg, hipStream_t stream)

@@ -60,18 +60,16 @@ struct Layout {
 static __constant__ TableSet c_tables = make_tables();
 
 // Full-rate gfx950 VALU forms (all operands in VGPRs).
+// v_bitop3_b32 computes any function of three inputs given as an 8-entry
+// truth table indexed by (src0 << 2) | (src1 << 1) | src2.
 __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t m, uint32_t b)
 {
-    uint32_t d;  // (a & m) | b
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xea" : "=v"(d) : "v"(a), "v"(m), "v"(b));
-    return d;
+    return __builtin_amdgcn_bitop3_b32(a, m, b, 0xea);  // (a & m) | b
 }
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
-    uint32_t d;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // a ^ b ^ c
 }
 
 // a ^ b ^ k with k uniform: k stays in an SGPR.  This is the half-rate form,
@@ -79,9 +77,7 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 // leaves room for more resident waves; the cost is 4 instructions per round.
 __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 {
-    uint32_t d;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
-    return d;
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
 template <int N>
@@ -141,37 +137,65 @@ struct LaneBases {
 };
 
 // Fill the replicated tables of one direction into LDS (whole workgroup).
+// Consecutive lanes write consecutive words (no bank conflicts); each thread
+// first issues up to kFillBatch independent loads of source words and only
+// then writes, so a fill costs a couple of memory round trips, not one per
+// word.
+constexpr uint32_t kFillBatch = 16;
+
 template <int PL, bool kDecrypt>
 __device__ __forceinline__ void fill_tables(uint32_t* lds, const TableSet* __restrict__ tabs)
 {
     using L = Layout<PL, kDecrypt>;
     const uint32_t* src = kDecrypt ? tabs->td0 : tabs->te0;
-    for (uint32_t w = threadIdx.x; w < L::table_bytes / 4; w += blockDim.x) {
-        uint32_t e, t;
-        if (PL == kPlace4) {
-            e = (w >> 6) & 255u;
-            t = (w >> 14) | (((w >> 5) & 1u) << 1);
-        } else if (PL == kPlace2) {
-            e = w >> 6;
-            t = ((w >> 5) & 1u) << 1;
-        } else {
-            e = w >> 5;
-            t = 0;
+    constexpr uint32_t n = L::table_bytes / 4;
+    const uint32_t step = blockDim.x;
+    for (uint32_t w0 = threadIdx.x; w0 < n; w0 += kFillBatch * step) {
+        uint32_t v[kFillBatch];
+#pragma unroll
+        for (uint32_t k = 0; k < kFillBatch; ++k) {
+            const uint32_t w = w0 + k * step;
+            uint32_t e;
+            if (PL == kPlace4)
+                e = (w >> 6) & 255u;
+            else if (PL == kPlace2)
+                e = (w >> 6) & 255u;
+            else
+                e = (w >> 5) & 255u;
+            v[k] = w < n ? src[e] : 0u;
         }
-        const uint32_t v = src[e];
-        lds[w] = t ? ((v << (8 * t)) | (v >> (32 - 8 * t))) : v;
+#pragma unroll
+        for (uint32_t k = 0; k < kFillBatch; ++k) {
+            const uint32_t w = w0 + k * step;
+            uint32_t t;
+            if (PL == kPlace4)
+                t = (w >> 14) | (((w >> 5) & 1u) << 1);
+            else if (PL == kPlace2)
+                t = ((w >> 5) & 1u) << 1;
+            else
+                t = 0;
+            if (w < n)
+                lds[w] = t ? ((v[k] << (8 * t)) | (v[k] >> (32 - 8 * t))) : v[k];
+        }
     }
     if (kDecrypt) {
-        for (uint32_t w = threadIdx.x; w < L::si_bytes / 4; w += blockDim.x) {
-            uint32_t v;
-            if (PL == kPlace4) {
-                v = tabs->si4[w >> 5];
-            } else {
-                const uint32_t q = 4u * (w >> 5);
-                v = uint32_t(tabs->inv_sbox[q]) | (uint32_t(tabs->inv_sbox[q + 1]) << 8) |
-                    (uint32_t(tabs->inv_sbox[q + 2]) << 16) | (uint32_t(tabs->inv_sbox[q + 3]) << 24);
+        constexpr uint32_t ns = L::si_bytes / 4;
+        for (uint32_t w0 = threadIdx.x; w0 < ns; w0 += kFillBatch * step) {
+            uint32_t v[kFillBatch];
+#pragma unroll
+            for (uint32_t k = 0; k < kFillBatch; ++k) {
+                const uint32_t w = w0 + k * step;
+                if (PL == kPlace4)
+                    v[k] = w < ns ? tabs->si4[(w >> 5) & 255u] : 0u;
+                else
+                    v[k] = w < ns ? tabs->si_packed[(w >> 5) & 63u] : 0u;
             }
-            lds[L::si_offset / 4 + w] = v;
+#pragma unroll
+            for (uint32_t k = 0; k < kFillBatch; ++k) {
+                const uint32_t w = w0 + k * step;
+                if (w < ns)
+                    lds[L::si_offset / 4 + w] = v[k];
+            }
         }
     }
 }

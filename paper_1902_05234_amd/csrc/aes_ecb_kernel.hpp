@@ -76,17 +76,15 @@ __global__ __launch_bounds__(1024) void ecb_kernel(const uint4* __restrict__ in,
     }
 }
 
-template <int NR, bool kDecrypt, int BPT, int PL>
-hipError_t launch_one(const void* in, void* out, uint64_t nblocks, const RoundKeys& rk, const LaunchShape& shape,
-                      int cus, hipStream_t stream)
+// Workgroups of a launch of kern over nblocks: shape.grid if set, else
+// persistent (as many as fit on every CU at once, given LDS and registers),
+// never more than the blocks can keep busy.
+inline hipError_t grid_for(const void* kern, const LaunchShape& shape, int cus, uint64_t nblocks, int* grid_out)
 {
-    auto kern = ecb_kernel<NR, kDecrypt, BPT, PL>;
     int grid = shape.grid;
     if (grid <= 0) {
-        // persistent: as many workgroups as fit on every CU at once (LDS and registers)
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
-                                                                   shape.wg, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, shape.wg, 0);
         if (e != hipSuccess)
             return e;
         grid = cus * (per_cu > 0 ? per_cu : 1);
@@ -95,6 +93,19 @@ hipError_t launch_one(const void* in, void* out, uint64_t nblocks, const RoundKe
     const uint64_t needed = (nblocks + per_group - 1) / per_group;
     if ((uint64_t)grid > needed)
         grid = (int)needed;
+    *grid_out = grid;
+    return hipSuccess;
+}
+
+template <int NR, bool kDecrypt, int BPT, int PL>
+hipError_t launch_one(const void* in, void* out, uint64_t nblocks, const RoundKeys& rk, const LaunchShape& shape,
+                      int cus, hipStream_t stream)
+{
+    auto kern = ecb_kernel<NR, kDecrypt, BPT, PL>;
+    int grid = 0;
+    hipError_t e = grid_for(reinterpret_cast<const void*>(kern), shape, cus, nblocks, &grid);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(shape.wg), 0, stream, static_cast<const uint4*>(in),
                        static_cast<uint4*>(out), nblocks, rk);
     return hipGetLastError();

@@ -23,6 +23,17 @@ hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decr
 
 hipError_t launch_copy(const void* in, void* out, uint64_t n16, int grid, hipStream_t stream);
 
+// A 128-bit big-endian counter block as two host integers (hi = bytes 0..7).
+struct Counter128 {
+    uint64_t hi;
+    uint64_t lo;
+};
+
+// CTR over nbytes (any length): data block j is XORed with the cipher of
+// counter c0 + j (mod 2^128).  rk is the encryption schedule.
+hipError_t launch_ctr(const LaunchShape& shape, int placement, int nr, const void* in, void* out, uint64_t nbytes,
+                      const Counter128& c0, const RoundKeys& rk, int cus, hipStream_t stream);
+
 // Work item of the batched kernel: one wave-sized chunk of one message.
 struct WorkItem {
     uint64_t in_block;
@@ -46,6 +57,12 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs& args, int bpt, int grid, int wg, hipStream_t stream);
+
+// Grid of a batch launch: at most max_grid workgroups, no more than the
+// items can keep busy, at least one per non-empty direction; enc_groups is
+// the requested split (< 0: by block share) clamped to that.
+void batch_grid(uint64_t n_enc, uint64_t n_dec, uint64_t enc_blocks, uint64_t total_blocks, int wg, int max_grid,
+                int requested_enc_groups, int* grid, int* enc_groups);
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();

@@ -1,0 +1,574 @@
+// aes_serve.cpp -- native continuous-batching request engine (aes_server_*).
+//
+// A worker thread owns the policy: requests submitted from any thread are
+// admitted in arrival order while the device budget (input + output bytes of
+// every admitted, unfinished request) and the output arena allow; whenever
+// one of the stream slots is free, everything admitted so far is planned into
+// work items (same planner as aes_batch_plan), copied to that slot's device
+// work list from pinned staging, and run as one persistent batch launch.
+// Slots are polled with events; a finished request releases its budget at
+// once and its output space when the caller releases it (or immediately with
+// auto_release).  All device memory (work lists, counters, arenas) comes
+// from the caller; the engine creates only streams and events.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/aesgpu.h"
+#include "aes_internal.hpp"
+
+namespace aesgpu {
+
+int device_cu_count();
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t id;
+    aes_request r;
+    double arrival = 0, admitted = 0, done = 0;
+    uint64_t out_block = 0;
+    int status = 0;
+    int batch = -1;
+};
+
+// First-fit allocator over [0, n) blocks with coalescing frees.
+class Arena {
+public:
+    explicit Arena(uint64_t n) : n_(n) { free_[0] = n; }
+    bool alloc(uint64_t len, uint64_t* start)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                *start = it->first;
+                const uint64_t rest = it->second - len, s = it->first + len;
+                free_.erase(it);
+                if (rest)
+                    free_[s] = rest;
+                used_ += len;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t start, uint64_t len)
+    {
+        used_ -= len;
+        auto it = free_.emplace(start, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return n_; }
+
+private:
+    uint64_t n_, used_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    aes_work_item* items_dev = nullptr;
+    uint32_t* counters_dev = nullptr;
+    aes_work_item* staging = nullptr;
+    std::vector<Req*> reqs;
+    bool busy = false;
+    double dry_done = 0;  // dry run: completion time
+};
+
+}  // namespace
+}  // namespace aesgpu
+
+struct aes_server {
+    aes_serve_config cfg{};
+    int device = 0;
+    int cus = 0;
+    const uint32_t* key_table = nullptr;
+    size_t n_slots = 0;
+    const void* in_pool = nullptr;
+    size_t in_blocks = 0;
+    void* out_arena = nullptr;
+    size_t out_blocks = 0;
+    std::vector<aesgpu::Slot> slots;
+    aesgpu::Arena arena{0};
+    aesgpu::Clock::time_point t0;
+
+    std::mutex mu;                         // guards incoming, completed, counters below
+    std::condition_variable cv;
+    std::deque<aesgpu::Req*> incoming;
+    std::vector<aesgpu::Req*> completed;
+    std::vector<std::pair<uint64_t, uint64_t>> releases;  // (out_block, nblocks) released by the caller
+    uint64_t next_id = 0;
+    bool stop = false;
+
+    // worker-only state
+    std::deque<aesgpu::Req*> pending;
+    uint64_t in_use = 0;
+    int batches = 0;
+    std::atomic<uint64_t> max_in_use{0};
+    std::atomic<int> last_error{AES_OK};
+    std::atomic<uint64_t> arena_used_pub{0}, pending_pub{0};  // published by the worker for aes_server_stats
+    std::atomic<uint64_t> submitted{0};                         // bumped by every submit and release
+    std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(aesgpu::Clock::now() - t0).count(); }
+};
+
+namespace aesgpu {
+namespace {
+
+void finish(aes_server* s, Slot& sl, int status, double t)
+{
+    std::vector<Req*> done;
+    done.swap(sl.reqs);
+    for (Req* q : done) {
+        q->done = t;
+        q->status = status;
+        s->in_use -= 2 * 16 * q->r.nblocks;
+        if (s->cfg.auto_release || status != AES_SERVED_DONE)
+            s->arena.release(q->out_block, q->r.nblocks);
+    }
+    sl.busy = false;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->completed.insert(s->completed.end(), done.begin(), done.end());
+}
+
+bool valid(const aes_server* s, const aes_request& r)
+{
+    return r.nblocks > 0 && 2 * 16 * r.nblocks <= s->cfg.budget_bytes && r.nblocks <= s->out_blocks &&
+           r.key_slot < s->n_slots && r.in_block <= s->in_blocks && r.nblocks <= s->in_blocks - r.in_block;
+}
+
+bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
+{
+    const uint32_t chunk = s->cfg.chunk_blocks;
+    size_t ne = 0, nd = 0;
+    uint64_t enc_b = 0, tot_b = 0;
+    for (Req* q : batch) {
+        const uint64_t c = (q->r.nblocks + chunk - 1) / chunk;
+        (q->r.decrypt ? nd : ne) += c;
+        tot_b += q->r.nblocks;
+        if (!q->r.decrypt)
+            enc_b += q->r.nblocks;
+    }
+    size_t ie = 0, id = ne;
+    for (Req* q : batch) {
+        for (uint64_t off = 0; off < q->r.nblocks; off += chunk) {
+            aes_work_item& it = sl.staging[q->r.decrypt ? id++ : ie++];
+            it.in_block = q->r.in_block + off;
+            it.out_block = q->out_block + off;
+            it.nblocks = (uint32_t)std::min<uint64_t>(chunk, q->r.nblocks - off);
+            it.key_slot = q->r.key_slot;
+        }
+    }
+    sl.reqs = batch;
+    sl.busy = true;
+    s->batches++;
+    if (s->cfg.dry_run) {
+        sl.dry_done = s->now() + s->cfg.dry_run_seconds;
+        return true;
+    }
+    const size_t n = ne + nd;
+    hipError_t e = hipMemcpyAsync(sl.items_dev, sl.staging, n * sizeof(aes_work_item), hipMemcpyHostToDevice,
+                                  sl.stream);
+    if (e == hipSuccess) {
+        int grid = 0, enc_groups = 0;
+        batch_grid(ne, nd, enc_b, tot_b, s->cfg.wg, s->cfg.grid > 0 ? s->cfg.grid : s->cus, -1, &grid,
+                   &enc_groups);
+        BatchArgs a{reinterpret_cast<const WorkItem*>(sl.items_dev), (uint32_t)ne, (uint32_t)nd, s->key_table,
+                    (uint32_t)s->n_slots, s->in_pool, s->out_arena, (uint64_t)s->in_blocks, (uint64_t)s->out_blocks,
+                    sl.counters_dev, (uint32_t)enc_groups};
+        e = launch_batch(a, s->cfg.bpt, grid, s->cfg.wg, sl.stream);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(sl.event, sl.stream);
+    if (e != hipSuccess) {
+        s->last_error.store(AES_EHIP);
+        finish(s, sl, AES_SERVED_FAILED, s->now());
+        return false;
+    }
+    return true;
+}
+
+void worker_main(aes_server* s)
+{
+    if (!s->cfg.dry_run)
+        hipSetDevice(s->device);
+    uint64_t seen = 0;
+    for (;;) {
+        bool stopping;
+        const bool idle = s->pending.empty() && std::none_of(s->slots.begin(), s->slots.end(),
+                                                             [](const Slot& x) { return x.busy; });
+        if (idle) {
+            // spin briefly before sleeping: a request arriving within ~50 us
+            // is picked up without a thread wake-up
+            const auto until = Clock::now() + std::chrono::microseconds(50);
+            while (s->submitted.load(std::memory_order_acquire) == seen && Clock::now() < until)
+                std::this_thread::yield();
+        }
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            if (idle && s->incoming.empty() && s->releases.empty() && !s->stop)
+                s->cv.wait_for(g, std::chrono::microseconds(200));
+            seen = s->submitted.load(std::memory_order_acquire);
+            while (!s->incoming.empty()) {
+                s->pending.push_back(s->incoming.front());
+                s->incoming.pop_front();
+            }
+            for (auto& rl : s->releases)
+                s->arena.release(rl.first, rl.second);
+            s->releases.clear();
+            stopping = s->stop;
+        }
+        // completions
+        for (Slot& sl : s->slots) {
+            if (!sl.busy)
+                continue;
+            if (s->cfg.dry_run) {
+                if (s->now() >= sl.dry_done)
+                    finish(s, sl, AES_SERVED_DONE, s->now());
+            } else {
+                hipError_t q = hipEventQuery(sl.event);
+                if (q == hipSuccess)
+                    finish(s, sl, AES_SERVED_DONE, s->now());
+                else if (q != hipErrorNotReady) {
+                    s->last_error.store(AES_EHIP);
+                    finish(s, sl, AES_SERVED_FAILED, s->now());
+                }
+            }
+        }
+        // admission into a free slot
+        for (Slot& sl : s->slots) {
+            if (sl.busy || s->pending.empty())
+                continue;
+            std::vector<Req*> batch;
+            uint64_t items = 0;
+            while (!s->pending.empty()) {
+                Req* q = s->pending.front();
+                if (!valid(s, q->r)) {  // can never run: report at once
+                    s->pending.pop_front();
+                    q->status = AES_SERVED_REJECTED;
+                    q->done = s->now();
+                    std::lock_guard<std::mutex> g(s->mu);
+                    s->completed.push_back(q);
+                    continue;
+                }
+                const uint64_t need = (q->r.nblocks + s->cfg.chunk_blocks - 1) / s->cfg.chunk_blocks;
+                const uint64_t bytes = 2 * 16 * q->r.nblocks;
+                if (items + need > s->cfg.max_batch_items || s->in_use + bytes > s->cfg.budget_bytes)
+                    break;
+                uint64_t start;
+                if (!s->arena.alloc(q->r.nblocks, &start))
+                    break;
+                s->pending.pop_front();
+                q->out_block = start;
+                q->admitted = s->now();
+                q->batch = s->batches;
+                s->in_use += bytes;
+                items += need;
+                batch.push_back(q);
+            }
+            if (batch.empty())
+                break;
+            if (s->in_use > s->max_in_use.load(std::memory_order_relaxed))
+                s->max_in_use.store(s->in_use, std::memory_order_relaxed);
+            launch(s, sl, batch);
+        }
+        s->arena_used_pub.store(s->arena.used(), std::memory_order_relaxed);
+        s->pending_pub.store(s->pending.size(), std::memory_order_relaxed);
+        if (stopping && s->pending.empty() &&
+            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot& x) { return x.busy; })) {
+            std::lock_guard<std::mutex> g(s->mu);
+            if (s->incoming.empty())
+                break;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace aesgpu
+
+using namespace aesgpu;
+
+extern "C" {
+
+size_t aes_server_workspace_bytes(const aes_serve_config* cfg)
+{
+    if (cfg == nullptr || cfg->nslots <= 0)
+        return 0;
+    const size_t items = ((size_t)cfg->max_batch_items * sizeof(aes_work_item) + 255) & ~(size_t)255;
+    return (size_t)cfg->nslots * (items + 256);
+}
+
+size_t aes_server_staging_bytes(const aes_serve_config* cfg)
+{
+    if (cfg == nullptr || cfg->nslots <= 0)
+        return 0;
+    return (size_t)cfg->nslots * cfg->max_batch_items * sizeof(aes_work_item);
+}
+
+int aes_server_create(const aes_serve_config* cfg, const uint32_t* key_table_dev, size_t n_slots,
+                      const void* in_pool, size_t in_blocks, void* out_arena, size_t out_blocks,
+                      void* workspace_dev, size_t workspace_bytes, void* staging_host, size_t staging_bytes,
+                      aes_server** out)
+{
+    if (out == nullptr || cfg == nullptr)
+        return AES_EINVAL;
+    *out = nullptr;
+    const aes_serve_config& c = *cfg;
+    if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.max_batch_items == 0 || c.budget_bytes == 0 ||
+        (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 || c.wg > 1024 || c.wg % 64)
+        return AES_EINVAL;
+    if (!c.dry_run && (key_table_dev == nullptr || in_pool == nullptr || out_arena == nullptr ||
+                       workspace_dev == nullptr || staging_host == nullptr))
+        return AES_EINVAL;
+    if (workspace_bytes < aes_server_workspace_bytes(cfg) || staging_bytes < aes_server_staging_bytes(cfg))
+        return AES_ERANGE;
+    if (n_slots == 0 || out_blocks == 0)
+        return AES_EINVAL;
+    aes_server* s = new (std::nothrow) aes_server();
+    if (!s)
+        return AES_ENOMEM;
+    s->cfg = c;
+    s->key_table = key_table_dev;
+    s->n_slots = n_slots;
+    s->in_pool = in_pool;
+    s->in_blocks = in_blocks;
+    s->out_arena = out_arena;
+    s->out_blocks = out_blocks;
+    s->arena = Arena(out_blocks);
+    s->slots.resize(c.nslots);
+    const size_t items_bytes = ((size_t)c.max_batch_items * sizeof(aes_work_item) + 255) & ~(size_t)255;
+    int rc = AES_OK;
+    if (!c.dry_run) {
+        if (hipGetDevice(&s->device) != hipSuccess)
+            rc = AES_EHIP;
+        s->cus = device_cu_count();
+        if (s->cus <= 0)
+            rc = AES_EHIP;
+    }
+    for (int i = 0; i < c.nslots && rc == AES_OK; ++i) {
+        Slot& sl = s->slots[i];
+        char* base = static_cast<char*>(workspace_dev) + (size_t)i * (items_bytes + 256);
+        sl.items_dev = reinterpret_cast<aes_work_item*>(base);
+        sl.counters_dev = reinterpret_cast<uint32_t*>(base + items_bytes);
+        sl.staging = reinterpret_cast<aes_work_item*>(static_cast<char*>(staging_host) +
+                                                      (size_t)i * c.max_batch_items * sizeof(aes_work_item));
+        if (c.dry_run)
+            continue;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess ||
+            hipMemsetAsync(sl.counters_dev, 0, 16, sl.stream) != hipSuccess)
+            rc = AES_EHIP;
+    }
+    if (rc == AES_OK && !c.dry_run) {
+        for (Slot& sl : s->slots)
+            if (hipStreamSynchronize(sl.stream) != hipSuccess)
+                rc = AES_EHIP;
+    }
+    if (rc != AES_OK) {
+        for (Slot& sl : s->slots) {
+            if (sl.event) hipEventDestroy(sl.event);
+            if (sl.stream) hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        return rc;
+    }
+    s->t0 = Clock::now();
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return AES_OK;
+}
+
+int aes_server_submit(aes_server* s, const aes_request* reqs, size_t n, uint64_t* first_id)
+{
+    if (s == nullptr || (n > 0 && reqs == nullptr))
+        return AES_EINVAL;
+    std::vector<Req*> made;
+    made.reserve(n);
+    const double t = s->now();
+    for (size_t i = 0; i < n; ++i) {
+        Req* q = new (std::nothrow) Req();
+        if (!q) {
+            for (Req* m : made)
+                delete m;
+            return AES_ENOMEM;
+        }
+        q->r = reqs[i];
+        q->arrival = t;
+        made.push_back(q);
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) {
+            for (Req* m : made)
+                delete m;
+            return AES_EBUSY;
+        }
+        if (first_id)
+            *first_id = s->next_id;
+        for (Req* q : made) {
+            q->id = s->next_id++;
+            s->incoming.push_back(q);
+        }
+        s->submitted.fetch_add(1, std::memory_order_release);
+    }
+    s->cv.notify_one();
+    return AES_OK;
+}
+
+int aes_server_poll(aes_server* s, aes_served* out, size_t cap, size_t* n)
+{
+    if (s == nullptr || n == nullptr || (cap > 0 && out == nullptr))
+        return AES_EINVAL;
+    std::vector<Req*> take;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        const size_t k = std::min(cap, s->completed.size());
+        take.assign(s->completed.begin(), s->completed.begin() + k);
+        s->completed.erase(s->completed.begin(), s->completed.begin() + k);
+    }
+    for (size_t i = 0; i < take.size(); ++i) {
+        const Req* q = take[i];
+        out[i].id = q->id;
+        out[i].arrival_s = q->arrival;
+        out[i].admitted_s = q->admitted;
+        out[i].done_s = q->done;
+        out[i].out_block = q->out_block;
+        out[i].nblocks = q->r.nblocks;
+        out[i].status = q->status;
+        out[i].batch = q->batch;
+        delete q;
+    }
+    *n = take.size();
+    return s->last_error.exchange(AES_OK) == AES_OK ? AES_OK : AES_EHIP;
+}
+
+int aes_server_release(aes_server* s, const aes_served* done, size_t n)
+{
+    if (s == nullptr || (n > 0 && done == nullptr))
+        return AES_EINVAL;
+    if (s->cfg.auto_release)
+        return AES_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (size_t i = 0; i < n; ++i)
+            if (done[i].status == AES_SERVED_DONE)
+                s->releases.emplace_back(done[i].out_block, done[i].nblocks);
+        s->submitted.fetch_add(1, std::memory_order_release);
+    }
+    s->cv.notify_one();
+    return AES_OK;
+}
+
+int aes_server_stats(aes_server* s, aes_serve_stats* st)
+{
+    if (s == nullptr || st == nullptr)
+        return AES_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    st->batches = (uint64_t)s->batches;
+    st->max_device_bytes_in_use = s->max_in_use.load(std::memory_order_relaxed);
+    st->arena_blocks_in_use = s->arena_used_pub.load(std::memory_order_relaxed);
+    st->pending = s->pending_pub.load(std::memory_order_relaxed) + s->incoming.size();
+    return AES_OK;
+}
+
+int aes_server_destroy(aes_server* s)
+{
+    if (s == nullptr)
+        return AES_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_one();
+    s->worker.join();
+    for (Slot& sl : s->slots) {
+        if (sl.stream)
+            hipStreamSynchronize(sl.stream);
+        if (sl.event)
+            hipEventDestroy(sl.event);
+        if (sl.stream)
+            hipStreamDestroy(sl.stream);
+    }
+    for (Req* q : s->completed)
+        delete q;
+    delete s;
+    return AES_OK;
+}
+
+int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arrival_s, size_t n, aes_served* results)
+{
+    if (s == nullptr || (n > 0 && (reqs == nullptr || arrival_s == nullptr || results == nullptr)))
+        return AES_EINVAL;
+    if (!s->cfg.auto_release)
+        return AES_EINVAL;
+    const double base = s->now();
+    std::vector<aes_served> buf(4096);
+    size_t got = 0, next = 0;
+    uint64_t id0 = 0;
+    bool have_id0 = false;
+    int rc = AES_OK;
+    while (got < n) {
+        const double t = s->now() - base;
+        size_t k = next;
+        while (k < n && arrival_s[k] <= t)
+            ++k;
+        if (k > next) {
+            uint64_t fid;
+            int r = aes_server_submit(s, reqs + next, k - next, &fid);
+            if (r != AES_OK)
+                return r;
+            if (!have_id0) {
+                id0 = fid;
+                have_id0 = true;
+            }
+            next = k;
+        }
+        size_t m = 0;
+        int pr = aes_server_poll(s, buf.data(), buf.size(), &m);
+        if (pr != AES_OK)
+            rc = pr;
+        for (size_t i = 0; i < m; ++i) {
+            const size_t idx = (size_t)(buf[i].id - id0);
+            if (idx < n) {
+                results[idx] = buf[i];
+                // open loop: latency is measured from the scheduled arrival
+                results[idx].arrival_s = base + arrival_s[idx];
+                ++got;
+            }
+        }
+        if (m == 0 && next < n) {
+            const double wait = arrival_s[next] - (s->now() - base);
+            if (wait > 200e-6)
+                std::this_thread::sleep_for(std::chrono::duration<double>(wait - 100e-6));
+        }
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -14,7 +14,8 @@
 //   Decryption tables (the paper measures decryption but gives no tables):
 //   Td0 for input w is ({0e}t, {09}t, {0d}t, {0b}t) with t = InvS(w), the
 //   columns of the inverse MixColumns matrix; Td_k = rotl(Td0, 8k).
-//   Si4 holds InvS(w) in all four bytes for the last decryption round.
+//   Si4 holds InvS(w) in all four bytes for the last decryption round, and
+//   si_packed four consecutive InvS bytes per word (the byte-packed table).
 #pragma once
 #include <cstdint>
 
@@ -28,6 +29,7 @@ struct TableSet {
     uint32_t te0[256];
     uint32_t td0[256];
     uint32_t si4[256];
+    uint32_t si_packed[64];  // InvS bytes 4q..4q+3 in one little-endian word
 };
 
 constexpr uint8_t rotl8(uint8_t v, int n) { return static_cast<uint8_t>((v << n) | (v >> (8 - n))); }
@@ -66,6 +68,9 @@ constexpr TableSet make_tables()
                    (uint32_t(gf_mul_log(t, v, 0x0d)) << 16) | (uint32_t(gf_mul_log(t, v, 0x0b)) << 24);
         t.si4[x] = uint32_t(v) * 0x01010101u;
     }
+    for (int q = 0; q < 64; ++q)
+        t.si_packed[q] = uint32_t(t.inv_sbox[4 * q]) | (uint32_t(t.inv_sbox[4 * q + 1]) << 8) |
+                         (uint32_t(t.inv_sbox[4 * q + 2]) << 16) | (uint32_t(t.inv_sbox[4 * q + 3]) << 24);
     return t;
 }
 

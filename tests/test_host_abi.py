@@ -202,6 +202,26 @@ def test_ecb_argument_checks_before_any_device_call():
     assert lib.aes_ecb_crypt_variant(rk, 10, 0, A, B, 4, None, None) == aes.AES_EINVAL
 
 
+def test_ctr_argument_checks_before_any_device_call():
+    lib = aes._lib()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    iv = (aes.ctypes.c_uint8 * 16)()
+    A, B = 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+    assert lib.aes_ctr_crypt(rk, 11, iv, 0, A, B, 64, None) == aes.AES_EINVAL
+    assert lib.aes_ctr_crypt(None, 10, iv, 0, A, B, 64, None) == aes.AES_EINVAL
+    assert lib.aes_ctr_crypt(rk, 10, None, 0, A, B, 64, None) == aes.AES_EINVAL
+    assert lib.aes_ctr_crypt(rk, 10, iv, 0, A, B, 0, None) == aes.AES_OK            # empty: no launch
+    assert lib.aes_ctr_crypt(rk, 10, iv, 0, None, B, 5, None) == aes.AES_EINVAL
+    assert lib.aes_ctr_crypt(rk, 10, iv, 0, A, None, 5, None) == aes.AES_EINVAL
+    assert lib.aes_ctr_crypt(rk, 10, iv, 0, A + 1, B, 5, None) == aes.AES_EALIGN
+    assert lib.aes_ctr_crypt(rk, 10, iv, 0, A, A + 16, 17, None) == aes.AES_EINVAL  # partial overlap
+    assert "overlap" in aes.aes_last_error()
+    for v in [aes.Variant(bpt=8), aes.Variant(wg=32), aes.Variant(placement=5), aes.Variant(grid=-2)]:
+        cv = v._c()
+        assert lib.aes_ctr_crypt_variant(rk, 10, iv, 0, A, B, 64, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
+    assert lib.aes_ctr_crypt_variant(rk, 10, iv, 0, A, B, 64, None, None) == aes.AES_EINVAL
+
+
 def test_tuning_table_round_trip():
     for nr in (10, 12, 14):
         for dec in (False, True):

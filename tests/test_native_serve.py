@@ -1,0 +1,157 @@
+"""The native serving engine (aes_server_*): admission policy, budget, arena
+and error paths in dry-run mode on the CPU; on the GPU every served result
+equals the same request run alone through the plain kernel, bit-exact."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1902_05234_amd import aes, inputs
+
+
+def requests(n, seed, max_blocks=3000, pool_blocks=200000, slots=8):
+    g = inputs.rng(60, seed)
+    r = np.zeros(n, dtype=aes.REQUEST_DTYPE)
+    r["nblocks"] = g.integers(1, max_blocks, n)
+    r["in_block"] = [int(g.integers(0, pool_blocks - nb)) for nb in r["nblocks"]]
+    r["key_slot"] = g.integers(0, slots, n)
+    r["decrypt"] = g.integers(0, 2, n)
+    return r
+
+
+def wait_all(srv, n, timeout=30.0):
+    got = []
+    t0 = time.time()
+    while sum(len(x) for x in got) < n:
+        got.append(srv.poll())
+        if time.time() - t0 > timeout:
+            raise AssertionError("requests did not finish")
+        time.sleep(0.0005)
+    out = np.concatenate(got)
+    return out[np.argsort(out["id"])]
+
+
+# ------------------------------------------------------------------ CPU part
+def test_dry_run_budget_fifo_and_overlap():
+    budget = 2 * 16 * 20000
+    srv = aes.Server(n_slots=8, in_blocks=200000, out_blocks=60000, budget_bytes=budget, chunk_blocks=256,
+                     max_batch_items=512, nslots=3, dry_run=True, dry_run_seconds=0.002)
+    r = requests(300, 1)
+    first = srv.submit(r)
+    out = wait_all(srv, 300)
+    st = srv.stats()
+    srv.close()
+    assert first == 0 and (out["id"] == np.arange(300)).all()
+    assert (out["status"] == aes.AES_SERVED_DONE).all()
+    assert st["max_device_bytes_in_use"] <= budget
+    assert st["arena_blocks_in_use"] == 0 and st["pending"] == 0
+    assert st["batches"] >= 10
+    assert (np.diff(out["admitted_s"]) >= 0).all(), "admission must follow submission order"
+    assert (out["done_s"] >= out["admitted_s"]).all() and (out["admitted_s"] >= out["arrival_s"]).all()
+    # requests of one batch share a batch index; batches are numbered in admission order
+    assert (np.diff(out["batch"]) >= 0).all()
+
+
+def test_dry_run_rejects_what_can_never_run():
+    srv = aes.Server(n_slots=4, in_blocks=10000, out_blocks=5000, budget_bytes=2 * 16 * 4000, chunk_blocks=64,
+                     max_batch_items=256, nslots=2, dry_run=True, dry_run_seconds=0.0005)
+    r = requests(40, 2, max_blocks=500, pool_blocks=10000, slots=4)
+    r[3]["nblocks"] = 0                 # empty
+    r[7]["nblocks"] = 4500              # over the budget
+    r[11]["key_slot"] = 9               # no such key slot
+    r[15]["in_block"] = 9990            # runs past the input pool
+    srv.submit(r)
+    out = wait_all(srv, 40)
+    srv.close()
+    bad = {3, 7, 11, 15}
+    for i in range(40):
+        assert out[i]["status"] == (aes.AES_SERVED_REJECTED if i in bad else aes.AES_SERVED_DONE), i
+
+
+def test_dry_run_manual_release_gates_the_arena():
+    srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=2000, budget_bytes=1 << 30, chunk_blocks=128,
+                     max_batch_items=64, nslots=2, auto_release=False, dry_run=True, dry_run_seconds=0.0002)
+    r = requests(30, 3, max_blocks=900, pool_blocks=100000, slots=2)
+    srv.submit(r)
+    done = []
+    t0 = time.time()
+    while len(done) < 30:
+        got = srv.poll()
+        if len(got):
+            # outputs in use never exceed the arena
+            assert srv.stats()["arena_blocks_in_use"] <= 2000
+            done.extend(got.tolist())
+            srv.release(got)
+        assert time.time() - t0 < 20
+        time.sleep(0.0005)
+    srv.close()
+    assert len(done) == 30
+
+
+def test_create_rejects_bad_configs():
+    for kw in (dict(nslots=0), dict(nslots=17), dict(chunk_blocks=0), dict(bpt=3), dict(wg=100),
+               dict(budget_bytes=0), dict(max_batch_items=0)):
+        args = dict(n_slots=1, in_blocks=10, out_blocks=10, dry_run=True)
+        args.update(kw)
+        with pytest.raises(aes.AesError):
+            aes.Server(**args)
+
+
+# ------------------------------------------------------------------ GPU part
+@pytest.mark.gpu
+def test_native_served_results_equal_the_request_alone(oracle_lib):
+    import torch
+    from paper_1902_05234_amd import batch
+    pool = inputs.key_pool(6, 32)
+    kt = batch.key_table([k for _, k in pool])
+    in_pool = inputs.device_random_bytes(6, 64 << 20)
+    out_arena = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda")
+    srv = aes.Server(kt, in_pool, out_arena, budget_bytes=512 << 20, chunk_blocks=256, max_batch_items=1 << 14,
+                     nslots=4, auto_release=False)
+    r = requests(500, 4, max_blocks=20000, pool_blocks=in_pool.numel() // 16, slots=len(pool))
+    srv.submit(r[:250])
+    time.sleep(0.001)
+    srv.submit(r[250:])                 # arrives while the first ones run
+    out = wait_all(srv, 500)
+    assert (out["status"] == aes.AES_SERVED_DONE).all()
+    assert srv.stats()["batches"] >= 2
+    scheds = [aes.aes_expand_key(k) for _, k in pool]
+    for i, q in enumerate(r):
+        ks = scheds[int(q["key_slot"])]
+        lo, n = int(q["in_block"]) * 16, int(q["nblocks"]) * 16
+        ob = int(out[i]["out_block"]) * 16
+        x = in_pool[lo:lo + n]
+        alone = torch.empty_like(x)
+        if q["decrypt"]:
+            aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, x, alone)
+        else:
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, alone)
+        assert torch.equal(alone, out_arena[ob:ob + n]), "request %d differs from the request alone" % i
+    for i in range(0, 500, 25):
+        q = r[i]
+        lo, n = int(q["in_block"]) * 16, min(int(q["nblocks"]), 2048) * 16
+        ob = int(out[i]["out_block"]) * 16
+        key = pool[int(q["key_slot"])][1]
+        x = in_pool[lo:lo + n].cpu().numpy()
+        want = oracle_lib.ecb_decrypt(key, x) if q["decrypt"] else oracle_lib.ecb_encrypt(key, x)
+        assert np.array_equal(out_arena[ob:ob + n].cpu().numpy(), want), i
+    srv.release(out)
+    srv.close()
+
+
+@pytest.mark.gpu
+def test_native_replay_reports_latency():
+    import torch
+    from paper_1902_05234_amd import batch
+    pool = inputs.key_pool(7, 64)
+    kt = batch.key_table([k for _, k in pool])
+    in_pool = inputs.device_random_bytes(7, 256 << 20)
+    out_arena = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    srv = aes.Server(kt, in_pool, out_arena, budget_bytes=1 << 30, chunk_blocks=1024, nslots=4)
+    r = requests(2000, 5, max_blocks=8000, pool_blocks=in_pool.numel() // 16, slots=len(pool))
+    arrival = np.cumsum(inputs.rng(61).exponential(20e-6, 2000))
+    out = srv.replay(r, arrival)
+    srv.close()
+    assert (out["status"] == aes.AES_SERVED_DONE).all()
+    lat = out["done_s"] - out["arrival_s"]
+    assert (lat > 0).all() and np.percentile(lat, 99) < 1.0
