@@ -55,6 +55,10 @@ class Oracle:
         lib.oracle_ctr_crypt.argtypes = [_p8, ctypes.c_int, _p8, ctypes.c_uint64, _p8, _p8, ctypes.c_uint64,
                                          ctypes.c_int]
         lib.oracle_ctr_crypt.restype = ctypes.c_int
+        lib.oracle_cbc_encrypt.argtypes = [_p8, ctypes.c_int, _p8, _p8, _p8, ctypes.c_uint64]
+        lib.oracle_cbc_encrypt.restype = ctypes.c_int
+        lib.oracle_cbc_decrypt.argtypes = [_p8, ctypes.c_int, _p8, _p8, _p8, ctypes.c_uint64, ctypes.c_int]
+        lib.oracle_cbc_decrypt.restype = ctypes.c_int
 
     # -- field ------------------------------------------------------------
     def xtime(self, a: int) -> int:
@@ -156,6 +160,34 @@ class Oracle:
                                         _ptr(out), src.size, int(nthreads))
         if rc != 0:
             raise ValueError("oracle rejected the key (%d bytes)" % len(key))
+        return out
+
+    def _cbc_args(self, key, iv, data):
+        key, iv = bytes(key), bytes(iv)
+        if len(iv) != 16:
+            raise ValueError("the initialisation vector is 16 bytes")
+        src = np.ascontiguousarray(np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray, memoryview)) else data, dtype=np.uint8).reshape(-1)
+        if src.size % 16:
+            raise ValueError("CBC input must be whole 16-byte blocks")
+        return (np.frombuffer(key, dtype=np.uint8).copy(), np.frombuffer(iv, dtype=np.uint8).copy(), src,
+                np.empty_like(src))
+
+    def cbc_encrypt(self, key: bytes, iv: bytes, data) -> np.ndarray:
+        """CBC encryption (sequential) of whole blocks."""
+        k, c, src, out = self._cbc_args(key, iv, data)
+        rc = self._lib.oracle_cbc_encrypt(_ptr(k), 8 * k.size, _ptr(c), _ptr(src), _ptr(out), src.size // 16)
+        if rc != 0:
+            raise ValueError("oracle rejected the key (%d bytes)" % k.size)
+        return out
+
+    def cbc_decrypt(self, key: bytes, iv: bytes, data, nthreads: int | None = None) -> np.ndarray:
+        """CBC decryption of whole blocks (threaded over block ranges)."""
+        k, c, src, out = self._cbc_args(key, iv, data)
+        nthreads = nthreads or (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+        rc = self._lib.oracle_cbc_decrypt(_ptr(k), 8 * k.size, _ptr(c), _ptr(src), _ptr(out), src.size // 16,
+                                          int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle rejected the key (%d bytes)" % k.size)
         return out
 
 

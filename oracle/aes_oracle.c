@@ -496,6 +496,105 @@ static int ctr(const uint8_t *key, int keybits, const uint8_t iv[16], uint64_t o
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------- CBC driver
+ *
+ * Cipher block chaining (section 3.1.2, eq 2).  The printed equation lacks
+ * the block cipher; the reading is the standard chain: C_i = cipher(P_i XOR
+ * C_{i-1}) with C_0 the initialisation vector, so decryption is P_i =
+ * invcipher(C_i) XOR C_{i-1}.  Encryption is sequential by definition and
+ * runs block after block on one thread; decryption of each block needs only
+ * two ciphertext blocks and is threaded over block ranges.  Whole blocks
+ * only.
+ */
+static int cbc_encrypt(const uint8_t *key, int keybits, const uint8_t iv[16], const uint8_t *in, uint8_t *out,
+                       uint64_t nblocks)
+{
+    uint8_t w[16 * 15], chain[16];
+    int nr;
+    if (expand_key(key, keybits, w, &nr) != ORACLE_OK || iv == NULL)
+        return ORACLE_EINVAL;
+    if (nblocks == 0)
+        return ORACLE_OK;
+    if (in == NULL || out == NULL)
+        return ORACLE_EINVAL;
+    memcpy(chain, iv, 16);
+    for (uint64_t b = 0; b < nblocks; ++b) {
+        uint8_t x[16];
+        for (int k = 0; k < 16; ++k)
+            x[k] = (uint8_t)(in[16 * b + k] ^ chain[k]);
+        cipher_block(w, nr, x, chain);
+        memcpy(out + 16 * b, chain, 16);
+    }
+    return ORACLE_OK;
+}
+
+typedef struct {
+    const uint8_t *w;
+    int nr;
+    const uint8_t *iv;
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t first, count;
+} cbc_job;
+
+static void *cbc_dec_worker(void *arg)
+{
+    const cbc_job *j = (const cbc_job *)arg;
+    const uint64_t stop = j->first + j->count;
+    for (uint64_t b = j->first; b < stop; ++b) {
+        uint8_t x[16];
+        const uint8_t *prev = b == 0 ? j->iv : j->in + 16 * (b - 1);
+        inv_cipher_block(j->w, j->nr, j->in + 16 * b, x);
+        for (int k = 0; k < 16; ++k)
+            j->out[16 * b + k] = (uint8_t)(x[k] ^ prev[k]);
+    }
+    return NULL;
+}
+
+static int cbc_decrypt(const uint8_t *key, int keybits, const uint8_t iv[16], const uint8_t *in, uint8_t *out,
+                       uint64_t nblocks, int nthreads)
+{
+    uint8_t w[16 * 15];
+    int nr;
+    if (expand_key(key, keybits, w, &nr) != ORACLE_OK || iv == NULL)
+        return ORACLE_EINVAL;
+    if (nblocks == 0)
+        return ORACLE_OK;
+    if (in == NULL || out == NULL || in == out)
+        return ORACLE_EINVAL; /* block b reads ciphertext block b - 1: no in-place */
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((uint64_t)nthreads > nblocks)
+        nthreads = (int)nblocks;
+    cbc_job *jobs = (cbc_job *)calloc((size_t)nthreads, sizeof(cbc_job));
+    pthread_t *tid = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tid) {
+        free(jobs);
+        free(tid);
+        return ORACLE_EINVAL;
+    }
+    uint64_t per = nblocks / (uint64_t)nthreads, extra = nblocks % (uint64_t)nthreads, next = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        uint64_t cnt = per + ((uint64_t)t < extra ? 1 : 0);
+        jobs[t] = (cbc_job){w, nr, iv, in, out, next, cnt};
+        next += cnt;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tid[t], NULL, cbc_dec_worker, &jobs[t]) != 0)
+            break;
+        started = t;
+    }
+    cbc_dec_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tid[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t)
+        cbc_dec_worker(&jobs[t]);
+    free(jobs);
+    free(tid);
+    return ORACLE_OK;
+}
+
 /* ---------------------------------------------------------- exported API */
 
 uint8_t oracle_xtime(uint8_t a) { return gf_xtime(a); }
@@ -579,4 +678,17 @@ int oracle_ctr_crypt(const uint8_t *key, int keybits, const uint8_t iv[16], uint
                      const uint8_t *in, uint8_t *out, uint64_t nbytes, int nthreads)
 {
     return ctr(key, keybits, iv, offset, in, out, nbytes, nthreads);
+}
+
+/* CBC over nblocks whole blocks with initialisation vector iv (C_0). */
+int oracle_cbc_encrypt(const uint8_t *key, int keybits, const uint8_t iv[16], const uint8_t *in, uint8_t *out,
+                       uint64_t nblocks)
+{
+    return cbc_encrypt(key, keybits, iv, in, out, nblocks);
+}
+
+int oracle_cbc_decrypt(const uint8_t *key, int keybits, const uint8_t iv[16], const uint8_t *in, uint8_t *out,
+                       uint64_t nblocks, int nthreads)
+{
+    return cbc_decrypt(key, keybits, iv, in, out, nblocks, nthreads);
 }

@@ -67,6 +67,15 @@ def openssl_ctr(key: bytes, iv: bytes, data: bytes) -> bytes:
     return r.stdout
 
 
+def openssl_cbc(key: bytes, iv: bytes, data: bytes, decrypt: bool) -> bytes:
+    """AES-CBC through the OpenSSL command-line tool, no padding."""
+    cmd = ["openssl", "enc", "-aes-%d-cbc" % (8 * len(key)), "-nopad", "-K", key.hex(), "-iv", iv.hex()]
+    if decrypt:
+        cmd.insert(2, "-d")
+    r = subprocess.run(cmd, input=data, capture_output=True, check=True)
+    return r.stdout
+
+
 def counter_blocks(iv: bytes, offset: int, n: int) -> np.ndarray:
     """n successive 128-bit big-endian counters from iv + offset, by Python integers."""
     c0 = int.from_bytes(iv, "big") + offset
@@ -327,6 +336,43 @@ def pin_ctr_structure(o):
     assert np.array_equal(got, o.ecb_encrypt(key, counter_blocks(iv, off, 6)))
 
 
+def pin_cbc_openssl(o):
+    """CBC (section 3.1.2, eq 2 read with the block cipher) against the
+    OpenSSL command-line tool, both directions, all key sizes."""
+    if not openssl_available():
+        raise AssertionError("openssl command-line tool not found")
+    for keybits in (128, 192, 256):
+        key = inputs.random_key(3500 + keybits, keybits)
+        iv = inputs.random_bytes(3501 + keybits, 16).tobytes()
+        for nblk in (1, 2, 37):
+            data = inputs.random_bytes(3502 + nblk, 16 * nblk).tobytes()
+            assert o.cbc_encrypt(key, iv, data).tobytes() == openssl_cbc(key, iv, data, False), (keybits, nblk)
+            assert o.cbc_decrypt(key, iv, data, nthreads=3).tobytes() == openssl_cbc(key, iv, data, True), (keybits, nblk)
+
+
+def pin_cbc_structure(o):
+    """CBC (eq 2): decryption inverts encryption; plaintext block i is the
+    ECB decryption of ciphertext block i XOR ciphertext block i-1 (the
+    initialisation vector for i = 1); the first ciphertext block is the ECB
+    encryption of P_1 XOR IV; changing ciphertext block i changes plaintext
+    blocks i and i+1 only; the thread count is irrelevant."""
+    for keybits in (128, 192, 256):
+        key = inputs.random_key(3600 + keybits, keybits)
+        iv = inputs.random_bytes(3601 + keybits, 16).tobytes()
+        ivn = np.frombuffer(iv, dtype=np.uint8)
+        x = inputs.random_bytes(3602 + keybits, 16 * 29)
+        c = o.cbc_encrypt(key, iv, x)
+        assert np.array_equal(o.cbc_decrypt(key, iv, c, nthreads=4), x)
+        assert np.array_equal(c[:16], o.ecb_encrypt(key, x[:16] ^ ivn))
+        prev = np.concatenate([ivn, c[:-16]])
+        assert np.array_equal(o.cbc_decrypt(key, iv, c, nthreads=1), o.ecb_decrypt(key, c) ^ prev)
+        c2 = c.copy()
+        c2[16 * 7 + 3] ^= 0x40
+        d2 = o.cbc_decrypt(key, iv, c2, nthreads=2).reshape(-1, 16)
+        changed = [i for i in range(29) if not np.array_equal(d2[i], x.reshape(-1, 16)[i])]
+        assert changed == [7, 8], changed
+
+
 ALL_PINS = [
     pin_paper_field_examples,
     pin_field_matches_polynomial_arithmetic,
@@ -341,7 +387,9 @@ ALL_PINS = [
     pin_openssl_known_answers,
     pin_ctr_structure,
     pin_ctr_openssl,
+    pin_cbc_structure,
+    pin_cbc_openssl,
 ]
 
 # pins that need the openssl command-line tool
-OPENSSL_PINS = (pin_openssl_known_answers, pin_ctr_openssl)
+OPENSSL_PINS = (pin_openssl_known_answers, pin_ctr_openssl, pin_cbc_openssl)

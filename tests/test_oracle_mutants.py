@@ -42,6 +42,12 @@ MUTANTS = [
     ("ctr_partial_block_dropped", "        if (n > 16)\n            n = 16;", "        if (n < 16)\n            n = 0;\n        if (n > 16)\n            n = 16;"),
     ("ctr_offset_ignored", "counter_add(iv, offset, ctr0);", "counter_add(iv, 0, ctr0);"),
     ("ctr_first_block_counter_plus_one", "counter_add(j->ctr0, b, ctr);", "counter_add(j->ctr0, b + 1, ctr);"),
+    ("cbc_chain_not_updated", "        cipher_block(w, nr, x, chain);\n        memcpy(out + 16 * b, chain, 16);",
+     "        uint8_t y[16];\n        cipher_block(w, nr, x, y);\n        memcpy(out + 16 * b, y, 16);"),
+    ("cbc_dec_xor_with_own_block", "const uint8_t *prev = b == 0 ? j->iv : j->in + 16 * (b - 1);",
+     "const uint8_t *prev = b == 0 ? j->iv : j->in + 16 * b;"),
+    ("cbc_dec_first_block_without_iv", "const uint8_t *prev = b == 0 ? j->iv : j->in + 16 * (b - 1);",
+     "static const uint8_t zero16[16];\n        const uint8_t *prev = b == 0 ? zero16 : j->in + 16 * (b - 1);"),
     ("ecb_last_block_skipped", "for (uint64_t b = j->first; b < j->first + j->count; ++b) {",
      "for (uint64_t b = j->first; b + 1 < j->first + j->count; ++b) {"),
 ]
