@@ -27,7 +27,6 @@ few bulk and copy launches (for rocprofv3).
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -64,23 +63,37 @@ def valu_floor_per_block(nr: int) -> int:
     return 24 * nr + 12                 # address/byte-select + XOR3 + final merge
 
 
+# Sources that define the plain ECB kernels (device code and launch shape);
+# a traffic figure taken on other versions of these is not reused.
+KERNEL_SOURCES = ["aes_device.hpp", "aes_tables.hpp", "aes_ecb_kernel.hpp", "aes_internal.hpp", "aes_ecb.hip",
+                  "aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1902_05234_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1902_05234_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(nbytes_payload: int):
+def kernel_instance(v) -> str:
+    """Template instance of the AES-128 encrypt kernel for variant v, as the
+    profiler names it."""
+    return "ecb_kernel<10, false, %d, %d>" % (v.bpt, v.placement)
+
+
+def read_traffic(nbytes_payload: int, instance: str):
     """HBM bytes per encrypt launch from the committed rocprofv3 PMC summary,
-    or None if it is missing or was taken on other kernel sources."""
+    or None if it is missing, was taken on other kernel sources or on another
+    kernel instance than the one the tuning table picks."""
     path = os.path.join(ROOT, "profiles", "aes128_ecb_encrypt_1GiB_pmc.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_hash:\s*(\w+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    k = re.search(r"kernel_instance:\s*(.+)", text)
+    if not m or not t or not k or m.group(1) != kernel_source_hash() or k.group(1).strip() != instance:
         return None
     return float(t.group(1))
 
@@ -241,6 +254,22 @@ def sweep(torch, aes, inputs, sizes):
         tm.run(fn)
     ms = sorted(tm.ms())[5]
     out["aes128_enc_%s_all_zero" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    # counter mode: same round core; the lookups depend on the counters only
+    fn = lambda: aes.aes_ctr_crypt(ks.rk_enc, ks.nr, bytes(range(16)), 0, xi, xo)
+    fn()
+    tm = Timer(torch)
+    for _ in range(10):
+        tm.run(fn)
+    ms = sorted(tm.ms())[5]
+    out["aes128_ctr_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    # CBC decryption: ECB decryption plus the XOR of the preceding ciphertext block
+    fn = lambda: aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, bytes(16), xi, xo)
+    fn()
+    tm = Timer(torch)
+    for _ in range(10):
+        tm.run(fn)
+    ms = sorted(tm.ms())[5]
+    out["aes128_cbc_dec_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
     del buf_in, buf_out
     torch.cuda.empty_cache()
     return out
@@ -382,6 +411,8 @@ def main():
         for _ in range(3):
             aes.aes_device_copy(x, y)
         ks = aes.aes_expand_key(inputs.random_key(1, 128))
+        for dec in (False, True):
+            log("variant", "decrypt" if dec else "encrypt", aes.aes_tune_get(10, dec, GiB // 16))
         for _ in range(max(1, args.steps)):
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
             aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, y, x)
@@ -391,7 +422,7 @@ def main():
 
     b = bulk(torch, aes, inputs, args)
     log("bulk: %.3f s for %d steps" % (b["elapsed"], args.steps))
-    traffic = read_traffic(b["nbytes"])
+    traffic = read_traffic(b["nbytes"], kernel_instance(aes.aes_tune_get(10, False, b["nbytes"] // 16)))
     result = {
         "metric": "AES-ECB enc/dec GB/s at 1 GiB + % roofline; batched vs plain GB/s; p99 latency",
         "value": round(2 * b["nbytes"] * args.steps / b["elapsed"] / 1e9, 2),

@@ -132,6 +132,26 @@ int aes_ctr_crypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, uint64_
                           void *out, size_t nbytes, const aes_variant *variant, void *stream);
 
 /*
+ * aes_cbc_decrypt -- CBC decryption (section 3.1.2, eq 2, read as
+ * C_i = cipher(P_i XOR C_{i-1}) with C_0 = iv): P_i = invcipher(C_i) XOR
+ * C_{i-1}.  Every block is independent, so this is the parallel direction
+ * of CBC; encryption is sequential within a message and is not offered.
+ *   rk:      host pointer to the DECRYPTION schedule (rk_dec), copied.
+ *   nr:      10, 12 or 14.
+ *   iv:      host pointer to the 16-byte initialisation vector (C_0).  To
+ *            continue a message, pass its last ciphertext block so far.
+ *   in, out: device pointers, 16-byte aligned, nblocks*16 bytes; they must
+ *            not overlap at all (in == out is AES_EINVAL: block b reads
+ *            ciphertext block b - 1).
+ *   nblocks: whole blocks; 0 is a no-op returning AES_OK.
+ * The variant is the decryption entry of the tuning table.
+ */
+int aes_cbc_decrypt(const uint32_t *rk, int nr, const uint8_t *iv, const void *in, void *out, size_t nblocks,
+                    void *stream);
+int aes_cbc_decrypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, const void *in, void *out, size_t nblocks,
+                            const aes_variant *variant, void *stream);
+
+/*
  * Batched ECB: many independent messages, each with its own key, key size
  * and direction, in one persistent launch (not in the paper; the same
  * per-block cipher as aes_ecb_encrypt/decrypt).

@@ -90,6 +90,9 @@ def _lib() -> ctypes.CDLL:
                 "aes_ctr_crypt": ([_u32p, _c_i, _u8p, ctypes.c_uint64, _c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_ctr_crypt_variant": ([_u32p, _c_i, _u8p, ctypes.c_uint64, _c_p, _c_p, _c_sz,
                                            ctypes.POINTER(_Variant), _c_p], _c_i),
+                "aes_cbc_decrypt": ([_u32p, _c_i, _u8p, _c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_cbc_decrypt_variant": ([_u32p, _c_i, _u8p, _c_p, _c_p, _c_sz, ctypes.POINTER(_Variant), _c_p],
+                                            _c_i),
                 "aes_tune_set": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_tune_get": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_size_bucket": ([_c_sz], _c_i),
@@ -110,7 +113,8 @@ def _lib() -> ctypes.CDLL:
 def exported_symbols():
     """Names this binding expects the library to export."""
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
-            "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
+            "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
+            "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
             "aes_ecb_batch", "aes_device_copy", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay"]
@@ -253,6 +257,34 @@ def aes_ctr_crypt_variant(rk, nr: int, iv: bytes, block_offset: int, inp, out, v
                           nbytes: int | None = None, stream=None):
     v = variant._c()
     return _ctr(_lib().aes_ctr_crypt_variant, rk, nr, iv, block_offset, inp, out, nbytes, stream, ctypes.byref(v))
+
+
+# ------------------------------------------------------------ CBC decryption
+def _cbc(fn, rk, nr, iv, inp, out, nblocks, stream, *extra):
+    n_in, n_out = _blocks_of(inp, "in"), _blocks_of(out, "out")
+    nblocks = n_in if nblocks is None else int(nblocks)
+    if nblocks > n_in or nblocks > n_out:
+        raise ValueError("nblocks=%d exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
+    iv = bytes(iv)
+    if len(iv) != 16:
+        raise ValueError("the initialisation vector is 16 bytes, got %d" % len(iv))
+    rk = _u32_array(rk, 4 * (int(nr) + 1))
+    ivb = (ctypes.c_uint8 * 16).from_buffer_copy(iv)
+    _check(fn(rk.ctypes.data_as(_u32p), int(nr), ivb, inp.data_ptr(), out.data_ptr(), nblocks, *extra,
+              _stream_handle(stream)))
+    return out
+
+
+def aes_cbc_decrypt(rk, nr: int, iv: bytes, inp, out, nblocks: int | None = None, stream=None):
+    """CBC decryption of whole blocks; rk is the decryption schedule; out
+    must not overlap inp."""
+    return _cbc(_lib().aes_cbc_decrypt, rk, nr, iv, inp, out, nblocks, stream)
+
+
+def aes_cbc_decrypt_variant(rk, nr: int, iv: bytes, inp, out, variant: Variant, nblocks: int | None = None,
+                            stream=None):
+    v = variant._c()
+    return _cbc(_lib().aes_cbc_decrypt_variant, rk, nr, iv, inp, out, nblocks, stream, ctypes.byref(v))
 
 
 def aes_tune_set(nr: int, decrypt: bool, nblocks: int, variant: Variant):

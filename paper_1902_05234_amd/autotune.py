@@ -38,7 +38,8 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _time(torch, fn, reps):
+def _times(torch, fn, reps):
+    """Durations (ms) of reps launches of fn, HIP events on the launch stream."""
     fn()
     s = torch.cuda.current_stream()
     evs = []
@@ -49,7 +50,11 @@ def _time(torch, fn, reps):
         b.record(s)
         evs.append((a, b))
     torch.cuda.synchronize()
-    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def _time(torch, fn, reps):
+    ms = sorted(_times(torch, fn, reps))
     return ms[len(ms) // 2]
 
 
@@ -60,8 +65,12 @@ def variants():
                 yield aes.Variant(bpt=b, wg=w, placement=p)
 
 
-def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, log=print):
-    """Time every variant on one (key size, direction, size); returns rows sorted by time."""
+def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, rounds: int = 3, log=print):
+    """Time every variant on one (key size, direction, size); returns rows
+    sorted by time.  The variants are timed in ``rounds`` interleaved passes
+    (reps launches each) and ranked by the median over all launches, so a
+    drift of the engine clock during the sweep does not favour whichever
+    variant ran first."""
     key = inputs.random_key(7, keybits)
     ks = aes.aes_expand_key(key)
     x = inputs.device_random_bytes(7, nbytes)
@@ -74,19 +83,27 @@ def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, 
     torch.cuda.synchronize()
     if not torch.equal(back, x):
         raise RuntimeError("reference variant does not round-trip")
-    rows = []
     out = torch.empty_like(x)
-    for v in variants():
+    vs = list(variants())
+    for v in vs:
         out.zero_()
         aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v)
         torch.cuda.synchronize()
         if not torch.equal(out, ref):
             raise RuntimeError("variant %s differs from the reference output" % (v,))
-        ms = _time(torch, lambda: aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v), reps)
+    times = {i: [] for i in range(len(vs))}
+    for _ in range(max(1, rounds)):
+        for i, v in enumerate(vs):
+            times[i] += _times(torch, lambda: aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v), reps)
+    rows = []
+    for i, v in enumerate(vs):
+        t = sorted(times[i])
+        ms = t[len(t) // 2]
         rows.append({"bpt": v.bpt, "wg": v.wg, "placement": v.placement, "ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9})
     rows.sort(key=lambda r: r["ms"])
-    log("  %d-bit %s %d B: best bpt=%d wg=%d %.1f GB/s (worst %.1f)" % (
-        keybits, "dec" if decrypt else "enc", nbytes, rows[0]["bpt"], rows[0]["wg"], rows[0]["GB_s"], rows[-1]["GB_s"]))
+    log("  %d-bit %s %d B: best bpt=%d wg=%d placement=%d %.1f GB/s (worst %.1f)" % (
+        keybits, "dec" if decrypt else "enc", nbytes, rows[0]["bpt"], rows[0]["wg"], rows[0]["placement"],
+        rows[0]["GB_s"], rows[-1]["GB_s"]))
     return rows
 
 
@@ -117,14 +134,14 @@ def tune_batch(torch, n_messages: int = 20000, chunks=(256, 1024, 4096), reps: i
     return rows
 
 
-def run(sizes=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, log=print):
+def run(sizes=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, rounds=3, log=print):
     import torch
     rec = {"device": torch.cuda.get_device_properties(0).name, "source_hash": source_hash(),
            "created": time.strftime("%Y-%m-%dT%H:%M:%S"), "plain": {}, "batch": None}
     for kb in key_sizes:
         for dec in (False, True):
             for n in sizes:
-                rows = tune_plain(torch, kb, dec, n, reps=reps, log=log)
+                rows = tune_plain(torch, kb, dec, n, reps=reps, rounds=rounds, log=log)
                 rec["plain"]["%d/%s/%d" % (kb, "dec" if dec else "enc", n)] = {"winner": rows[0], "all": rows}
     if batch_too:
         rec["batch"] = tune_batch(torch, log=log)
@@ -153,13 +170,16 @@ def main(argv=None):
     ap.add_argument("--out", default="aesgpu_tune.json")
     ap.add_argument("--quick", action="store_true", help="AES-256 decrypt of 256 MiB plus the batch mix only")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=10, help="launches per variant per round")
+    ap.add_argument("--rounds", type=int, default=3, help="interleaved passes over the variants")
+    ap.add_argument("--sizes", default=None, help="comma-separated byte sizes (default: one per size bucket)")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     if a.quick:
-        rec = run(sizes=(256 << 20,), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, log=log)
+        rec = run(sizes=(256 << 20,), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds, log=log)
     else:
-        rec = run(batch_too=not a.no_batch, reps=a.reps, log=log)
+        sizes = tuple(int(x) for x in a.sizes.split(",")) if a.sizes else BUCKET_SIZES
+        rec = run(sizes=sizes, batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds, log=log)
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
     log("wrote", a.out)

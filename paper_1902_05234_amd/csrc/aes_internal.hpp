@@ -34,6 +34,12 @@ struct Counter128 {
 hipError_t launch_ctr(const LaunchShape& shape, int placement, int nr, const void* in, void* out, uint64_t nbytes,
                       const Counter128& c0, const RoundKeys& rk, int cus, hipStream_t stream);
 
+// CBC decryption of nblocks: block b is invcipher(in[b]) XOR in[b - 1]
+// (iv for block 0).  rk is the decryption schedule; out must not alias in.
+hipError_t launch_cbc_decrypt(const LaunchShape& shape, int placement, int nr, const void* in, void* out,
+                              uint64_t nblocks, const uint8_t iv[16], const RoundKeys& rk, int cus,
+                              hipStream_t stream);
+
 // Work item of the batched kernel: one wave-sized chunk of one message.
 struct WorkItem {
     uint64_t in_block;

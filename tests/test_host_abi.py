@@ -222,6 +222,24 @@ def test_ctr_argument_checks_before_any_device_call():
     assert lib.aes_ctr_crypt_variant(rk, 10, iv, 0, A, B, 64, None, None) == aes.AES_EINVAL
 
 
+def test_cbc_argument_checks_before_any_device_call():
+    lib = aes._lib()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    iv = (aes.ctypes.c_uint8 * 16)()
+    A, B = 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+    assert lib.aes_cbc_decrypt(rk, 13, iv, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_cbc_decrypt(None, 10, iv, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_cbc_decrypt(rk, 10, None, A, B, 4, None) == aes.AES_EINVAL
+    assert lib.aes_cbc_decrypt(rk, 10, iv, A, B, 0, None) == aes.AES_OK             # empty: no launch
+    assert lib.aes_cbc_decrypt(rk, 10, iv, A, A, 4, None) == aes.AES_EINVAL         # in place
+    assert "in place" in aes.aes_last_error()
+    assert lib.aes_cbc_decrypt(rk, 10, iv, A, A + 32, 4, None) == aes.AES_EINVAL    # partial overlap
+    assert lib.aes_cbc_decrypt(rk, 10, iv, A + 8, B, 4, None) == aes.AES_EALIGN
+    cv = aes.Variant(bpt=3)._c()
+    assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL
+    assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, None, None) == aes.AES_EINVAL
+
+
 def test_tuning_table_round_trip():
     for nr in (10, 12, 14):
         for dec in (False, True):
