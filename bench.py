@@ -15,13 +15,18 @@ before timing starts.  Prints ONE JSON line:
                bounded slice of the same workload
   batched      20,000 mixed messages in one persistent launch (graph replay)
                vs per-message plain launches and vs the bulk-equivalent rate
-  sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB
+  sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB, plus
+               an all-zero control, CTR and CBC decryption at 1 GiB
+  host_path    the paper's file sizes (1,202 ... 1,190,402 bytes) host buffer
+               in, host buffer out (copies included), pinned and pageable,
+               beside the paper's own GPU times; and the 1 GiB pinned rate
   serving      open-loop Poisson requests (80 % 64 B-16 KiB, 20 % 1-64 MiB,
                4,096 resident keys, 32 GiB device budget) at offered loads
                rho x the batched rate: p50/p99 latency and sustained GB/s
 
 Flags: --gpus N (only 1 is supported), --steps K, --warmup W,
---no-batch / --no-sweep / --no-cpu to skip sections, --profile to run only a
+--no-batch / --no-sweep / --no-cpu / --no-host / --no-serve to skip sections,
+--profile to run only a
 few bulk and copy launches (for rocprofv3).
 """
 from __future__ import annotations
@@ -34,6 +39,8 @@ import platform
 import re
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -63,10 +70,10 @@ def valu_floor_per_block(nr: int) -> int:
     return 24 * nr + 12                 # address/byte-select + XOR3 + final merge
 
 
-# Sources that define the plain ECB kernels (device code and launch shape);
-# a traffic figure taken on other versions of these is not reused.
-KERNEL_SOURCES = ["aes_device.hpp", "aes_tables.hpp", "aes_ecb_kernel.hpp", "aes_internal.hpp", "aes_ecb.hip",
-                  "aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip"]
+# Sources that hold the device code of the plain ECB kernels; a traffic
+# figure taken on other versions of these is not reused.
+KERNEL_SOURCES = ["aes_device.hpp", "aes_tables.hpp", "aes_ecb_kernel.hpp", "aes_ecb_p4.hip", "aes_ecb_p2.hip",
+                  "aes_ecb_p1.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -279,6 +286,63 @@ def size_name(n):
     return "%dGiB" % (n // GiB) if n >= GiB else "%dMiB" % (n // MiB)
 
 
+# The paper's GPU times (seconds) per file size, GeForce 940MX, files in host
+# memory (section 5, Table 4 encryption, Table 5 decryption): context only.
+PAPER_GPU_SECONDS = {
+    1202: (0.000732, 0.000771), 4652: (0.000770, 0.000821), 9302: (0.000784, 0.000790),
+    18602: (0.000807, 0.000821), 37202: (0.000886, 0.000918), 74402: (0.001048, 0.001040),
+    148802: (0.001302, 0.001331), 297602: (0.001896, 0.002018), 595202: (0.003145, 0.003577),
+    1190402: (0.005316, 0.005847),
+}
+
+
+def host_sweep(torch, aes, inputs, reps=20):
+    """The paper's file sizes through the host-inclusive path (host buffer in,
+    host buffer out; AES-128, sizes padded to whole blocks), pinned and
+    pageable host buffers, plus one 1 GiB pinned buffer for the rate over the
+    host link.  Wall time of the synchronous call, median of reps."""
+    ks = aes.aes_expand_key(inputs.random_key(5, 128))
+    pipe = aes.HostPipe(chunk_bytes=4 * MiB, nslots=4, staging=True)
+    out = {"keybits": 128, "chunk_bytes": 4 * MiB, "nslots": 4, "sizes": []}
+    big = max(PAPER_GPU_SECONDS)
+    src_pin = torch.from_numpy(inputs.random_bytes(6, (big + 15) // 16 * 16)).pin_memory()
+    dst_pin = torch.empty_like(src_pin).pin_memory()
+    src_pg = src_pin.numpy().copy()
+    dst_pg = np.empty_like(src_pg)
+
+    def timed(op, a, b):
+        pipe.run(op, ks, a, out=b)
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pipe.run(op, ks, a, out=b)
+            t.append(time.perf_counter() - t0)
+        return sorted(t)[reps // 2]
+
+    for size, (p_enc, p_dec) in sorted(PAPER_GPU_SECONDS.items()):
+        n = (size + 15) // 16 * 16
+        row = {"bytes": size, "padded": n, "paper_940MX_s": {"enc": p_enc, "dec": p_dec}}
+        for mode, a, b in (("pinned", src_pin[:n], dst_pin[:n]), ("pageable", src_pg[:n], dst_pg[:n])):
+            te = timed(aes.AES_PIPE_ECB_ENCRYPT, a, b)
+            td = timed(aes.AES_PIPE_ECB_DECRYPT, a, b)
+            row[mode] = {"enc_s": round(te, 7), "dec_s": round(td, 7), "enc_GB_s": round(n / te / 1e9, 3),
+                         "dec_GB_s": round(n / td / 1e9, 3)}
+        out["sizes"].append(row)
+    del src_pin, dst_pin
+    # 1 GiB host-resident, pinned: the rate over the host link (not the headline value)
+    x = torch.from_numpy(inputs.random_bytes(7, 64 * MiB)).repeat(16).pin_memory()
+    y = torch.empty_like(x).pin_memory()
+    pipe.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x, out=y)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        pipe.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x, out=y)
+        ts.append(time.perf_counter() - t0)
+    out["pinned_1GiB_encrypt_GB_s"] = round(GiB / sorted(ts)[2] / 1e9, 2)
+    pipe.close()
+    return out
+
+
 def batched(torch, aes, inputs, bulk_rates):
     from paper_1902_05234_amd import batch
     mix = inputs.message_mix(2, 20000)
@@ -384,6 +448,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-inclusive file-size sweep")
     ap.add_argument("--serve-levels", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9,1.0")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--profile", action="store_true", help="only a few copy and bulk launches (for rocprofv3)")
@@ -457,6 +522,9 @@ def main():
         log("sweep done")
         if not args.no_sweep:
             result["sweep_GB_s"] = rates
+    if not args.no_host:
+        result["host_path"] = host_sweep(torch, aes, inputs)
+        log("host path done")
     if not args.no_batch:
         result["batched"] = batched(torch, aes, inputs, rates)
         log("batched done")

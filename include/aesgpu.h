@@ -152,6 +152,59 @@ int aes_cbc_decrypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, const
                             const aes_variant *variant, void *stream);
 
 /*
+ * Host-inclusive path (aes_pipe_*): host buffer in, host buffer out.  The
+ * paper's GPU timings are of files in host memory (section 5, Tables 4-5),
+ * i.e. they include the copies over the host link; this path measures and
+ * serves that regime.  A buffer is cut into chunks; chunk i runs on slot
+ * i mod nslots (one stream): copy to the device, the kernel in place,
+ * copy back, so copies and kernels of different chunks overlap.
+ *
+ * aes_pipe_config (all memory provided and owned by the caller):
+ *   dev, dev_bytes:         device workspace, 16-byte aligned, at least
+ *                           nslots * chunk_bytes bytes.
+ *   pinned, pinned_bytes:   pinned host staging (hipHostMalloc / page-locked)
+ *                           of at least nslots * chunk_bytes bytes; used for
+ *                           pageable host buffers.  May be NULL when every
+ *                           run passes AES_PIPE_HOST_PINNED.
+ *   chunk_bytes:            positive multiple of 16.
+ *   nslots:                 1..AES_PIPE_MAX_SLOTS streams (chunks in flight).
+ * aes_pipe_create records the current device and creates the streams and
+ * events; aes_pipe_destroy waits for them and frees them (not the memory).
+ *
+ * aes_pipe_run(p, op, rk, nr, iv, host_in, host_out, nbytes, flags):
+ *   op:      AES_PIPE_ECB_ENCRYPT / AES_PIPE_ECB_DECRYPT (rk = rk_enc /
+ *            rk_dec, nbytes a multiple of 16) or AES_PIPE_CTR (rk = rk_enc,
+ *            iv = first counter block, any nbytes; chunk k continues the
+ *            counter at iv + k*chunk_bytes/16).
+ *   host_in, host_out: host pointers; host_in == host_out is allowed, any
+ *            other overlap is AES_EINVAL.
+ *   flags:   AES_PIPE_HOST_PINNED if both host buffers are page-locked (then
+ *            they are copied directly, no staging).
+ * Synchronous: returns when host_out holds the result.  Calls on one pipe
+ * are serialised.  Errors: AES_EINVAL for bad arguments, AES_EHIP for a
+ * failed copy or launch (all slots are drained before returning).
+ */
+#define AES_PIPE_MAX_SLOTS 8
+#define AES_PIPE_ECB_ENCRYPT 0
+#define AES_PIPE_ECB_DECRYPT 1
+#define AES_PIPE_CTR 2
+#define AES_PIPE_HOST_PINNED 1
+typedef struct aes_pipe aes_pipe;
+typedef struct {
+    void *dev;
+    uint64_t dev_bytes;
+    void *pinned;
+    uint64_t pinned_bytes;
+    uint64_t chunk_bytes;
+    int32_t nslots;
+    int32_t reserved; /* 0 */
+} aes_pipe_config;
+int aes_pipe_create(const aes_pipe_config *cfg, aes_pipe **out);
+int aes_pipe_destroy(aes_pipe *p);
+int aes_pipe_run(aes_pipe *p, int op, const uint32_t *rk, int nr, const uint8_t *iv, const void *host_in,
+                 void *host_out, size_t nbytes, int flags);
+
+/*
  * Batched ECB: many independent messages, each with its own key, key size
  * and direction, in one persistent launch (not in the paper; the same
  * per-block cipher as aes_ecb_encrypt/decrypt).

@@ -117,7 +117,8 @@ def exported_symbols():
             "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
             "aes_ecb_batch", "aes_device_copy", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
-            "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay"]
+            "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
+            "aes_pipe_destroy", "aes_pipe_run"]
 
 
 def aes_last_error() -> str:
@@ -513,3 +514,99 @@ class Server:
 def _check_rc(rc: int, what: str):
     if rc != AES_OK:
         raise AesError(rc, "%s failed (%s)" % (what, aes_last_error() or "see argument checks"))
+
+
+# ------------------------------------------------------- host-inclusive path
+AES_PIPE_ECB_ENCRYPT = 0
+AES_PIPE_ECB_DECRYPT = 1
+AES_PIPE_CTR = 2
+AES_PIPE_HOST_PINNED = 1
+AES_PIPE_MAX_SLOTS = 8
+
+
+class _PipeConfig(ctypes.Structure):
+    _fields_ = [("dev", _c_p), ("dev_bytes", ctypes.c_uint64), ("pinned", _c_p), ("pinned_bytes", ctypes.c_uint64),
+                ("chunk_bytes", ctypes.c_uint64), ("nslots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _pipe_sigs(lib):
+    if getattr(lib, "_pipe_sigs", False):
+        return
+    lib.aes_pipe_create.argtypes = [ctypes.POINTER(_PipeConfig), ctypes.POINTER(_c_p)]
+    lib.aes_pipe_create.restype = _c_i
+    lib.aes_pipe_destroy.argtypes = [_c_p]
+    lib.aes_pipe_destroy.restype = _c_i
+    lib.aes_pipe_run.argtypes = [_c_p, _c_i, _u32p, _c_i, _u8p, _c_p, _c_p, _c_sz, _c_i]
+    lib.aes_pipe_run.restype = _c_i
+    lib._pipe_sigs = True
+
+
+def _host_view(a, name):
+    """(pointer, nbytes, pinned) of a host uint8 numpy array or CPU torch tensor."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.uint8 or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("%s must be a contiguous uint8 array" % name)
+        return a.ctypes.data, a.size, False
+    import torch
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or a.dtype != torch.uint8 or not a.is_contiguous():
+            raise ValueError("%s must be a contiguous uint8 CPU tensor" % name)
+        return a.data_ptr(), a.numel(), bool(a.is_pinned())
+    raise TypeError("%s must be a numpy array or a CPU torch tensor" % name)
+
+
+class HostPipe:
+    """The host-inclusive path (aes_pipe_* in aesgpu.h): host buffers in and
+    out, chunks pipelined over ``nslots`` streams.  The device workspace and
+    the pinned staging are allocated here with torch and kept alive."""
+
+    def __init__(self, chunk_bytes: int = 4 << 20, nslots: int = 4, staging: bool = True):
+        import torch
+        lib = _lib()
+        _pipe_sigs(lib)
+        self._lib = lib
+        n = int(chunk_bytes) * int(nslots)
+        self._dev = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self._pin = torch.empty(n, dtype=torch.uint8, pin_memory=True) if staging else None
+        torch.cuda.synchronize()
+        self.cfg = _PipeConfig(self._dev.data_ptr(), n, None if self._pin is None else self._pin.data_ptr(),
+                               0 if self._pin is None else n, int(chunk_bytes), int(nslots), 0)
+        h = _c_p()
+        _check(lib.aes_pipe_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, op: int, ks: KeySchedule, src, out=None, iv: bytes | None = None):
+        """Encrypt (AES_PIPE_ECB_ENCRYPT), decrypt (AES_PIPE_ECB_DECRYPT) or
+        CTR-process (AES_PIPE_CTR, with ``iv``) a host buffer; returns ``out``
+        (a new numpy array if not given).  Pinned CPU tensors on both sides are
+        copied without staging."""
+        if self._h is None:
+            raise RuntimeError("pipe is closed")
+        if out is None:
+            out = np.empty(src.size if isinstance(src, np.ndarray) else src.numel(), dtype=np.uint8)
+        sp, sn, spin = _host_view(src, "src")
+        op_, on, opin = _host_view(out, "out")
+        if on < sn:
+            raise ValueError("out holds %d bytes, src %d" % (on, sn))
+        rk = ks.rk_dec if op == AES_PIPE_ECB_DECRYPT else ks.rk_enc
+        rk = _u32_array(rk, 4 * (ks.nr + 1))
+        ivb = None
+        if op == AES_PIPE_CTR:
+            iv = bytes(iv if iv is not None else bytes(16))
+            if len(iv) != 16:
+                raise ValueError("the counter block is 16 bytes")
+            ivb = (ctypes.c_uint8 * 16).from_buffer_copy(iv)
+        flags = AES_PIPE_HOST_PINNED if (spin and opin) else 0
+        _check(self._lib.aes_pipe_run(self._h, int(op), rk.ctypes.data_as(_u32p), int(ks.nr), ivb, sp, op_, sn, flags))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._lib.aes_pipe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,9 +19,6 @@
 #include "aes_tables.hpp"
 
 namespace aesgpu {
-namespace {
-
-constexpr TableSet kHostTables = make_tables();
 
 thread_local char g_err[512] = "";
 
@@ -38,6 +35,10 @@ int fail_hip(hipError_t e, const char* what)
 {
     return fail(AES_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+namespace {
+
+constexpr TableSet kHostTables = make_tables();
 
 int rounds_for_bits(int keybits)
 {

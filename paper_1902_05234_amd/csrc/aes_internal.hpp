@@ -73,4 +73,9 @@ void batch_grid(uint64_t n_enc, uint64_t n_dec, uint64_t enc_blocks, uint64_t to
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// Record the message of a failure for aes_last_error() (calling thread) and
+// return code; fail_hip formats a HIP error.
+int fail(int code, const char* fmt, ...);
+int fail_hip(hipError_t e, const char* what);
+
 }  // namespace aesgpu

@@ -1,0 +1,255 @@
+// aes_pipe.cpp -- host-inclusive path (aes_pipe_*): host buffer in, host
+// buffer out.
+//
+// The paper times files in host memory (section 5, Tables 4-5), so its GPU
+// figures include the copies over the host link.  This path runs the same
+// kernels on host buffers: the buffer is cut into chunks, and chunk i goes
+// through slot i mod N (one stream, one device chunk, one pinned staging
+// chunk per slot): host -> device copy, the kernel in place on the device
+// chunk, device -> host copy, an event.  Chunks on different slots overlap,
+// so copies in both directions and kernels run at once.  Pageable buffers go
+// through the slot's pinned chunk (a CPU copy on each side); buffers the
+// caller allocated pinned (AES_PIPE_HOST_PINNED) are copied directly.  The
+// caller provides the device workspace and the pinned staging; the pipe
+// creates only streams and events.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/aesgpu.h"
+#include "aes_internal.hpp"
+
+namespace aesgpu {
+namespace {
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    uint8_t* dev = nullptr;
+    uint8_t* pin = nullptr;
+    // chunk in flight on this slot, whose output still has to leave the pinned chunk
+    bool pending = false;
+    uint64_t off = 0, len = 0;
+};
+
+}  // namespace
+}  // namespace aesgpu
+
+struct aes_pipe {
+    int device = 0;
+    uint64_t chunk = 0;
+    bool has_pinned = false;
+    std::vector<aesgpu::Slot> slots;
+    std::mutex mu;  // one run at a time per pipe
+};
+
+using namespace aesgpu;
+
+namespace {
+
+void destroy_slots(aes_pipe* p)
+{
+    for (auto& s : p->slots) {
+        if (s.event)
+            hipEventDestroy(s.event);
+        if (s.stream)
+            hipStreamDestroy(s.stream);
+    }
+    p->slots.clear();
+}
+
+bool overlap_partial(const void* a, const void* b, uint64_t n)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x != y && x < y + n && y < x + n;
+}
+
+// copy the finished chunk of slot s from its pinned chunk to the caller's buffer
+int finish(Slot& s, uint8_t* host_out, bool staged)
+{
+    if (!s.pending)
+        return AES_OK;
+    hipError_t e = hipEventSynchronize(s.event);
+    if (e != hipSuccess)
+        return fail_hip(e, "pipe: waiting for a chunk");
+    if (staged)
+        std::memcpy(host_out + s.off, s.pin, s.len);
+    s.pending = false;
+    return AES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aes_pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
+{
+    if (out == nullptr || cfg == nullptr)
+        return fail(AES_EINVAL, "null config or output pointer");
+    *out = nullptr;
+    if (cfg->chunk_bytes == 0 || cfg->chunk_bytes % 16u)
+        return fail(AES_EINVAL, "chunk_bytes must be a positive multiple of 16, got %llu",
+                    (unsigned long long)cfg->chunk_bytes);
+    if (cfg->nslots < 1 || cfg->nslots > AES_PIPE_MAX_SLOTS)
+        return fail(AES_EINVAL, "nslots must be in [1, %d], got %d", AES_PIPE_MAX_SLOTS, cfg->nslots);
+    const uint64_t need = cfg->chunk_bytes * (uint64_t)cfg->nslots;
+    if (cfg->dev == nullptr || cfg->dev_bytes < need)
+        return fail(AES_EINVAL, "device workspace must hold nslots * chunk_bytes = %llu bytes",
+                    (unsigned long long)need);
+    if ((reinterpret_cast<uintptr_t>(cfg->dev) & 15u) || (cfg->chunk_bytes & 15u))
+        return fail(AES_EALIGN, "device workspace must be 16-byte aligned");
+    if (cfg->pinned != nullptr && cfg->pinned_bytes < need)
+        return fail(AES_EINVAL, "pinned staging must hold nslots * chunk_bytes = %llu bytes (or be NULL)",
+                    (unsigned long long)need);
+    aes_pipe* p = new (std::nothrow) aes_pipe;
+    if (p == nullptr)
+        return fail(AES_ENOMEM, "pipe: out of host memory");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "pipe: current device");
+    }
+    p->chunk = cfg->chunk_bytes;
+    p->has_pinned = cfg->pinned != nullptr;
+    p->slots.resize((size_t)cfg->nslots);
+    for (int i = 0; i < cfg->nslots; ++i) {
+        Slot& s = p->slots[(size_t)i];
+        s.dev = static_cast<uint8_t*>(cfg->dev) + (uint64_t)i * cfg->chunk_bytes;
+        s.pin = p->has_pinned ? static_cast<uint8_t*>(cfg->pinned) + (uint64_t)i * cfg->chunk_bytes : nullptr;
+        if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming)) != hipSuccess) {
+            destroy_slots(p);
+            delete p;
+            return fail_hip(e, "pipe: stream or event creation");
+        }
+    }
+    *out = p;
+    return AES_OK;
+}
+
+int aes_pipe_destroy(aes_pipe* p)
+{
+    if (p == nullptr)
+        return AES_OK;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (auto& s : p->slots)
+            if (s.stream)
+                hipStreamSynchronize(s.stream);
+        destroy_slots(p);
+    }
+    delete p;
+    return AES_OK;
+}
+
+int aes_pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t* iv, const void* host_in,
+                 void* host_out, size_t nbytes, int flags)
+{
+    if (p == nullptr)
+        return fail(AES_EINVAL, "null pipe");
+    if (op != AES_PIPE_ECB_ENCRYPT && op != AES_PIPE_ECB_DECRYPT && op != AES_PIPE_CTR)
+        return fail(AES_EINVAL, "unknown pipe operation %d", op);
+    if (nr != 10 && nr != 12 && nr != 14)
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (rk == nullptr || (op == AES_PIPE_CTR && iv == nullptr))
+        return fail(AES_EINVAL, "null round-key or counter pointer");
+    if (op != AES_PIPE_CTR && nbytes % 16u)
+        return fail(AES_EINVAL, "ECB takes whole 16-byte blocks, got %zu bytes", nbytes);
+    if (nbytes == 0)
+        return AES_OK;
+    if (host_in == nullptr || host_out == nullptr)
+        return fail(AES_EINVAL, "null host buffer with nbytes=%zu", nbytes);
+    if (overlap_partial(host_in, host_out, nbytes))
+        return fail(AES_EINVAL, "host in and out overlap without being the same buffer");
+    const bool staged = !(flags & AES_PIPE_HOST_PINNED);
+    if (staged && !p->has_pinned)
+        return fail(AES_EINVAL, "pageable host buffers need pinned staging in the pipe config");
+
+    std::lock_guard<std::mutex> lk(p->mu);
+    int prev_dev = 0;
+    hipGetDevice(&prev_dev);
+    if (prev_dev != p->device)
+        hipSetDevice(p->device);
+    int cus = device_cu_count();
+    if (cus <= 0) {
+        if (prev_dev != p->device)
+            hipSetDevice(prev_dev);
+        return fail(AES_EHIP, "cannot query the pipe's device");
+    }
+    RoundKeys keys{};
+    std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
+    Counter128 c0{0, 0};
+    if (op == AES_PIPE_CTR)
+        for (int i = 0; i < 8; ++i) {
+            c0.hi = (c0.hi << 8) | iv[i];
+            c0.lo = (c0.lo << 8) | iv[8 + i];
+        }
+    const uint8_t* src = static_cast<const uint8_t*>(host_in);
+    uint8_t* dst = static_cast<uint8_t*>(host_out);
+    const size_t ns = p->slots.size();
+    int rc = AES_OK;
+    uint64_t chunk_index = 0;
+    for (uint64_t off = 0; off < nbytes && rc == AES_OK; off += p->chunk, ++chunk_index) {
+        Slot& s = p->slots[chunk_index % ns];
+        rc = finish(s, dst, staged);
+        if (rc != AES_OK)
+            break;
+        const uint64_t len = nbytes - off < p->chunk ? nbytes - off : p->chunk;
+        const void* h2d_src = src + off;
+        if (staged) {
+            std::memcpy(s.pin, src + off, len);
+            h2d_src = s.pin;
+        }
+        hipError_t e = hipMemcpyAsync(s.dev, h2d_src, len, hipMemcpyHostToDevice, s.stream);
+        if (e != hipSuccess) {
+            rc = fail_hip(e, "pipe: host to device copy");
+            break;
+        }
+        const uint64_t blocks = (len + 15u) / 16u;
+        aes_variant v;
+        aes_tune_get(nr, op == AES_PIPE_ECB_DECRYPT ? 1 : 0, blocks, &v);
+        const LaunchShape shape{v.bpt, v.wg, 0};
+        if (op == AES_PIPE_CTR) {
+            Counter128 c = c0;
+            const uint64_t lo = c.lo + off / 16u;
+            c.hi += lo < c.lo ? 1u : 0u;
+            c.lo = lo;
+            e = launch_ctr(shape, v.placement, nr, s.dev, s.dev, len, c, keys, cus, s.stream);
+        } else {
+            e = launch_ecb(shape, v.placement, nr, op == AES_PIPE_ECB_DECRYPT, s.dev, s.dev, blocks, keys, cus,
+                           s.stream);
+        }
+        if (e != hipSuccess) {
+            rc = fail_hip(e, "pipe: kernel launch");
+            break;
+        }
+        e = hipMemcpyAsync(staged ? static_cast<void*>(s.pin) : static_cast<void*>(dst + off), s.dev, len,
+                           hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(s.event, s.stream);
+        if (e != hipSuccess) {
+            rc = fail_hip(e, "pipe: device to host copy");
+            break;
+        }
+        s.off = off;
+        s.len = len;
+        s.pending = true;
+    }
+    // drain every slot (also after an error, so no copy into the caller's
+    // buffers is still running when the call returns)
+    for (auto& s : p->slots) {
+        const int r = finish(s, dst, staged && rc == AES_OK);
+        if (rc == AES_OK)
+            rc = r;
+        s.pending = false;
+    }
+    if (prev_dev != p->device)
+        hipSetDevice(prev_dev);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""The host-inclusive path (aes_pipe_*): host buffer in, host buffer out,
+chunks pipelined over several streams.  Bit-exact against the CPU oracle:
+the paper's file sizes (section 5, Tables 4-5, padded to whole blocks for
+ECB), pageable buffers through the pinned staging and pinned buffers copied
+directly, chunk boundaries that cut through the data, CTR with a partial
+last block and a counter continued across chunks, and in-place host
+buffers."""
+import numpy as np
+import pytest
+
+from paper_1902_05234_amd import aes, inputs
+from tests.gpu_util import cuda, first_mismatch
+
+pytestmark = pytest.mark.gpu
+
+PAPER_SIZES = [1202, 4652, 9302, 18602, 37202, 74402, 148802, 297602, 595202, 1190402]
+
+
+def assert_same(got, want, what):
+    i = first_mismatch(np.asarray(got), np.asarray(want))
+    assert i is None, "%s: first differing byte %d" % (what, i)
+
+
+def padded(n):
+    return (n + 15) // 16 * 16
+
+
+@pytest.fixture(scope="module")
+def pipe():
+    cuda()
+    p = aes.HostPipe(chunk_bytes=64 << 10, nslots=3)
+    yield p
+    p.close()
+
+
+@pytest.mark.parametrize("keybits", [128, 256])
+def test_pipe_paper_sizes_pageable(oracle_lib, pipe, keybits):
+    key = inputs.random_key(800, keybits)
+    ks = aes.aes_expand_key(key)
+    for size in PAPER_SIZES:
+        x = inputs.random_bytes(801 + size, padded(size))
+        c = pipe.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x)
+        assert_same(c, oracle_lib.ecb_encrypt(key, x), "enc %d" % size)
+        assert_same(pipe.run(aes.AES_PIPE_ECB_DECRYPT, ks, c), x, "dec %d" % size)
+
+
+def test_pipe_pinned_direct_and_in_place(oracle_lib):
+    torch = cuda()
+    key = inputs.random_key(810, 192)
+    ks = aes.aes_expand_key(key)
+    n = 16 * 300001
+    x = inputs.random_bytes(811, n)
+    p = aes.HostPipe(chunk_bytes=1 << 20, nslots=4, staging=False)
+    try:
+        src = torch.from_numpy(x.copy()).pin_memory()
+        dst = torch.empty(n, dtype=torch.uint8).pin_memory()
+        p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, src, out=dst)
+        assert_same(dst.numpy(), oracle_lib.ecb_encrypt(key, x), "pinned enc")
+        p.run(aes.AES_PIPE_ECB_DECRYPT, ks, dst, out=dst)          # in place
+        assert_same(dst.numpy(), x, "pinned dec in place")
+        with pytest.raises(aes.AesError):                          # pageable without staging
+            p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x)
+    finally:
+        p.close()
+
+
+def test_pipe_ctr_across_chunks(oracle_lib, pipe):
+    key = inputs.random_key(820, 128)
+    ks = aes.aes_expand_key(key)
+    iv = bytes(8) + b"\xff" * 7 + b"\xf0"        # the low half carries inside the buffer
+    for n in (1, 17, (64 << 10) * 3 + 5, (64 << 10) * 7 - 3):
+        x = inputs.random_bytes(821 + n, n)
+        y = pipe.run(aes.AES_PIPE_CTR, ks, x, iv=iv)
+        assert_same(y, oracle_lib.ctr_crypt(key, iv, x), "ctr n=%d" % n)
+        buf = x.copy()
+        pipe.run(aes.AES_PIPE_CTR, ks, buf, out=buf, iv=iv)        # in place, staged
+        assert_same(buf, y, "ctr in place n=%d" % n)
+
+
+def test_pipe_large_buffer_many_chunks(oracle_lib):
+    """64 MiB + 48 B through 4 MiB chunks on 4 streams against the device path."""
+    torch = cuda()
+    key = inputs.random_key(830, 256)
+    ks = aes.aes_expand_key(key)
+    n = (64 << 20) + 48
+    x = inputs.random_bytes(831, n)
+    p = aes.HostPipe(chunk_bytes=4 << 20, nslots=4)
+    try:
+        c = p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x)
+    finally:
+        p.close()
+    xd = torch.from_numpy(x).to("cuda")
+    want = torch.empty_like(xd)
+    aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xd, want)
+    assert_same(c, want.cpu().numpy(), "64 MiB")
+    assert_same(c[-(1 << 20):], oracle_lib.ecb_encrypt(key, x[-(1 << 20):]), "last MiB vs oracle")

@@ -240,6 +240,32 @@ def test_cbc_argument_checks_before_any_device_call():
     assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, None, None) == aes.AES_EINVAL
 
 
+def test_pipe_config_checks_before_any_device_call():
+    lib = aes._lib()
+    aes._pipe_sigs(lib)
+    h = aes.ctypes.c_void_p()
+    A, P = 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+
+    def create(**kw):
+        c = dict(dev=A, dev_bytes=1 << 20, pinned=P, pinned_bytes=1 << 20, chunk_bytes=1 << 18, nslots=4, reserved=0)
+        c.update(kw)
+        cfg = aes._PipeConfig(**c)
+        return lib.aes_pipe_create(aes.ctypes.byref(cfg), aes.ctypes.byref(h))
+
+    assert lib.aes_pipe_create(None, aes.ctypes.byref(h)) == aes.AES_EINVAL
+    assert create(chunk_bytes=0) == aes.AES_EINVAL
+    assert create(chunk_bytes=1000) == aes.AES_EINVAL
+    assert create(nslots=0) == aes.AES_EINVAL
+    assert create(nslots=aes.AES_PIPE_MAX_SLOTS + 1) == aes.AES_EINVAL
+    assert create(dev_bytes=(1 << 20) - 16) == aes.AES_EINVAL
+    assert create(dev=None) == aes.AES_EINVAL
+    assert create(pinned_bytes=1 << 19) == aes.AES_EINVAL
+    assert create(dev=A + 8) == aes.AES_EALIGN
+    assert "16-byte" in aes.aes_last_error()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    assert lib.aes_pipe_run(None, 0, rk, 10, None, A, A, 16, 0) == aes.AES_EINVAL
+
+
 def test_tuning_table_round_trip():
     for nr in (10, 12, 14):
         for dec in (False, True):
