@@ -83,6 +83,9 @@ int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_
 #define AES_PLACEMENT_TTABLE4 0 /* four T-tables, 32 replicas each, in LDS (128 KiB) */
 #define AES_PLACEMENT_TTABLE2 1 /* T0 and T2 (= T0 rotated 16), 32 replicas (64 KiB) */
 #define AES_PLACEMENT_TTABLE1 2 /* T0 only, 32 replicas (32 KiB); rotations on the VALU */
+#define AES_PLACEMENT_BITSLICED 3 /* no tables: 32 blocks per lane as 128 bit slices, the S-box as a
+                                     Boolean circuit; ECB only, bpt is ignored (512 bytes per thread),
+                                     wg at most 256 */
 typedef struct {
     int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes) */
     int32_t wg;        /* workgroup size: multiple of 64 in [64, 1024] */

@@ -26,7 +26,9 @@ from . import aes, inputs
 
 BPTS = (1, 2, 4)
 WGS = (64, 128, 256, 512, 1024)
-PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1)
+PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1,
+              aes.AES_PLACEMENT_BITSLICED)
+BITSLICE_MAX_WG = 256
 # representative sizes of the tuning buckets (bytes)
 BUCKET_SIZES = (4 << 10, 64 << 10, 1 << 20, 8 << 20, 256 << 20)
 
@@ -58,11 +60,20 @@ def _time(torch, fn, reps):
     return ms[len(ms) // 2]
 
 
-def variants():
+def variants(log=None):
+    """The search space.  The bitsliced placement always takes 32 blocks per
+    lane (bpt does not apply) and at most 256-thread workgroups; the
+    combinations it cannot run are skipped and logged once."""
+    skipped = []
     for p in PLACEMENTS:
         for b in BPTS:
             for w in WGS:
+                if p == aes.AES_PLACEMENT_BITSLICED and (b != 1 or w > BITSLICE_MAX_WG):
+                    skipped.append((p, b, w))
+                    continue
                 yield aes.Variant(bpt=b, wg=w, placement=p)
+    if log is not None and skipped:
+        log("  skipped %d bitsliced combinations (bpt does not apply; wg <= %d)" % (len(skipped), BITSLICE_MAX_WG))
 
 
 def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, rounds: int = 3, log=print):
@@ -84,7 +95,7 @@ def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, 
     if not torch.equal(back, x):
         raise RuntimeError("reference variant does not round-trip")
     out = torch.empty_like(x)
-    vs = list(variants())
+    vs = list(variants(log))
     for v in vs:
         out.zero_()
         aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v)

@@ -142,8 +142,11 @@ int check_variant(const aes_variant* v)
     if (v->wg < 64 || v->wg > 1024 || (v->wg % 64) != 0)
         return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", v->wg);
     if (v->placement != AES_PLACEMENT_TTABLE4 && v->placement != AES_PLACEMENT_TTABLE2 &&
-        v->placement != AES_PLACEMENT_TTABLE1)
+        v->placement != AES_PLACEMENT_TTABLE1 && v->placement != AES_PLACEMENT_BITSLICED)
         return fail(AES_EINVAL, "placement %d is not built in this library", v->placement);
+    if (v->placement == AES_PLACEMENT_BITSLICED && v->wg > kBitsliceMaxWg)
+        return fail(AES_EINVAL, "the bitsliced placement takes workgroups of at most %d threads, got %d",
+                    kBitsliceMaxWg, v->wg);
     if (v->grid < 0)
         return fail(AES_EINVAL, "grid must be >= 0 (0 = persistent default), got %d", v->grid);
     return AES_OK;
@@ -177,6 +180,17 @@ int run_ecb(const uint32_t* rk, int nr, bool decrypt, const void* in, void* out,
     return AES_OK;
 }
 
+// CTR and CBC run on the table placements; a bitsliced tuning entry (ECB
+// only) is replaced by the 2-table kernel with 32 bytes per thread.
+void table_variant(aes_variant* v)
+{
+    if (v->placement == AES_PLACEMENT_BITSLICED) {
+        v->placement = AES_PLACEMENT_TTABLE2;
+        v->bpt = 2;
+        v->wg = 1024;
+    }
+}
+
 int run_ctr(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset, const void* in, void* out,
             size_t nbytes, const aes_variant* v, void* stream)
 {
@@ -197,6 +211,8 @@ int run_ctr(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset
     int rc = check_variant(v);
     if (rc != AES_OK)
         return rc;
+    if (v->placement == AES_PLACEMENT_BITSLICED)
+        return fail(AES_EINVAL, "CTR runs on the table placements only");
     // c0 = iv + block_offset as a 128-bit big-endian sum
     Counter128 c0{0, 0};
     for (int i = 0; i < 8; ++i) {
@@ -235,6 +251,8 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     rc = check_variant(v);
     if (rc != AES_OK)
         return rc;
+    if (v->placement == AES_PLACEMENT_BITSLICED)
+        return fail(AES_EINVAL, "CBC decryption runs on the table placements only");
     RoundKeys keys{};
     std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
     int cus = device_cu_count();
@@ -362,6 +380,7 @@ int aes_ctr_crypt(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_
     if (!valid_nr(nr))
         return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
     aes_tune_get(nr, 0, (nbytes + 15u) / 16u, &v);
+    table_variant(&v);
     return run_ctr(rk, nr, iv, block_offset, in, out, nbytes, &v, stream);
 }
 
@@ -380,6 +399,7 @@ int aes_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     if (!valid_nr(nr))
         return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
     aes_tune_get(nr, 1, nblocks, &v);
+    table_variant(&v);
     return run_cbc_decrypt(rk, nr, iv, in, out, nblocks, &v, stream);
 }
 

@@ -21,6 +21,7 @@ hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decr
     case 0: return launch_ecb_p4(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);
     case 1: return launch_ecb_p2(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);
     case 2: return launch_ecb_p1(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);
+    case 3: return launch_bitslice(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -23,6 +23,12 @@ hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decr
 
 hipError_t launch_copy(const void* in, void* out, uint64_t n16, int grid, hipStream_t stream);
 
+// Bitsliced placement (no tables): 32 blocks per lane, workgroups of at most
+// kBitsliceMaxWg threads (the slices take most of the register file).
+constexpr int kBitsliceMaxWg = 256;
+hipError_t launch_bitslice(const LaunchShape& shape, int nr, bool decrypt, const void* in, void* out,
+                           uint64_t nblocks, const RoundKeys& rk, int cus, hipStream_t stream);
+
 // A 128-bit big-endian counter block as two host integers (hi = bytes 0..7).
 struct Counter128 {
     uint64_t hi;

@@ -212,6 +212,11 @@ int aes_pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t*
         const uint64_t blocks = (len + 15u) / 16u;
         aes_variant v;
         aes_tune_get(nr, op == AES_PIPE_ECB_DECRYPT ? 1 : 0, blocks, &v);
+        if (op == AES_PIPE_CTR && v.placement == AES_PLACEMENT_BITSLICED) {
+            v.placement = AES_PLACEMENT_TTABLE2;  // CTR runs on the table placements
+            v.bpt = 2;
+            v.wg = 1024;
+        }
         const LaunchShape shape{v.bpt, v.wg, 0};
         if (op == AES_PIPE_CTR) {
             Counter128 c = c0;
