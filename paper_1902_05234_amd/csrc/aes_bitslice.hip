@@ -24,21 +24,52 @@ namespace aesgpu {
 
 constexpr int kSlicedBlocks = 32;  // blocks per lane
 
-// In place: afterwards bit c of a[r] is the former bit r of a[c].
-__device__ __forceinline__ void transpose32(uint32_t a[32])
+// Masks of the bit-level transpose stages, kept in VGPRs so that every
+// v_bitop3_b32 operand is a VGPR (the full-rate form).
+struct TransposeMasks {
+    uint32_t m4, m2, m1;
+    __device__ __forceinline__ TransposeMasks()
+    {
+        asm volatile("v_mov_b32 %0, 0x0f0f0f0f" : "=v"(m4));
+        asm volatile("v_mov_b32 %0, 0x33333333" : "=v"(m2));
+        asm volatile("v_mov_b32 %0, 0x55555555" : "=v"(m1));
+    }
+};
+
+// In place: afterwards bit c of a[r] is the former bit r of a[c].  Five
+// stages exchange the off-diagonal sub-blocks of 16, 8, 4, 2 and 1 bits
+// between rows k and k + s.  The 16- and 8-bit stages move whole halves or
+// bytes, one v_perm_b32 per result row; the bit stages are a shift and a
+// select, (m ? x : y) being the bitop3 table 0xca.
+__device__ __forceinline__ void transpose32(uint32_t a[32], const TransposeMasks& tm)
 {
 #pragma unroll
-    for (int lvl = 0; lvl < 5; ++lvl) {
-        const int s = 16 >> lvl;
-        const uint32_t m = lvl == 0 ? 0x0000ffffu : lvl == 1 ? 0x00ff00ffu : lvl == 2 ? 0x0f0f0f0fu
-                         : lvl == 3 ? 0x33333333u : 0x55555555u;
+    for (int k = 0; k < 16; ++k) {  // rows k, k + 16: [a0 a1 b0 b1], [a2 a3 b2 b3] in 16-bit halves
+        const uint32_t x = a[k], y = a[k + 16];
+        a[k] = __builtin_amdgcn_perm(y, x, 0x05040100u);
+        a[k + 16] = __builtin_amdgcn_perm(y, x, 0x07060302u);
+    }
+#pragma unroll
+    for (int g = 0; g < 32; g += 16) {
+#pragma unroll
+        for (int k = g; k < g + 8; ++k) {  // bytes: [x0 y0 x2 y2], [x1 y1 x3 y3]
+            const uint32_t x = a[k], y = a[k + 8];
+            a[k] = __builtin_amdgcn_perm(y, x, 0x06020400u);
+            a[k + 8] = __builtin_amdgcn_perm(y, x, 0x07030501u);
+        }
+    }
+#pragma unroll
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        const int s = 4 >> lvl;
+        const uint32_t m = lvl == 0 ? tm.m4 : lvl == 1 ? tm.m2 : tm.m1;
 #pragma unroll
         for (int g = 0; g < 32; g += 2 * s) {
 #pragma unroll
             for (int k = g; k < g + s; ++k) {
-                const uint32_t t = ((a[k] >> s) ^ a[k + s]) & m;
-                a[k + s] ^= t;
-                a[k] ^= t << s;
+                const uint32_t x = a[k], y = a[k + s];
+                const uint32_t ys = s == 1 ? y + y : y << s;
+                a[k + s] = __builtin_amdgcn_bitop3_b32(m, x >> s, y, 0xca);
+                a[k] = __builtin_amdgcn_bitop3_b32(m, x, ys, 0xca);
             }
         }
     }
@@ -60,7 +91,7 @@ __device__ __forceinline__ void set_comp(uint4& v, int c, uint32_t x)
 // Blocks first + 64 j (j < 32) of the lane into slices; missing blocks are zero.
 template <bool kGuard>
 __device__ __forceinline__ void load_slices(const uint4* __restrict__ in, uint64_t first, uint64_t nblocks,
-                                            uint32_t s[128])
+                                            uint32_t s[128], const TransposeMasks& tm)
 {
     uint4 v[kSlicedBlocks];
 #pragma unroll
@@ -74,7 +105,7 @@ __device__ __forceinline__ void load_slices(const uint4* __restrict__ in, uint64
 #pragma unroll
         for (int j = 0; j < 32; ++j)
             w[j] = comp(v[j], c);
-        transpose32(w);
+        transpose32(w, tm);
 #pragma unroll
         for (int b = 0; b < 32; ++b)
             s[32 * c + b] = w[b];
@@ -83,7 +114,7 @@ __device__ __forceinline__ void load_slices(const uint4* __restrict__ in, uint64
 
 template <bool kGuard>
 __device__ __forceinline__ void store_slices(uint4* __restrict__ out, uint64_t first, uint64_t nblocks,
-                                             const uint32_t s[128])
+                                             const uint32_t s[128], const TransposeMasks& tm)
 {
     uint4 v[kSlicedBlocks];
 #pragma unroll
@@ -92,7 +123,7 @@ __device__ __forceinline__ void store_slices(uint4* __restrict__ out, uint64_t f
 #pragma unroll
         for (int b = 0; b < 32; ++b)
             w[b] = s[32 * c + b];
-        transpose32(w);
+        transpose32(w, tm);
 #pragma unroll
         for (int j = 0; j < 32; ++j)
             set_comp(v[j], c, w[j]);
@@ -255,20 +286,21 @@ __global__ __launch_bounds__(256, 2) void bitslice_kernel(const uint4* __restric
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves_per_grid = (uint64_t)gridDim.x * (blockDim.x >> 6);
     constexpr uint64_t span = 64u * kSlicedBlocks;
+    const TransposeMasks tm;
     for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv * span < nblocks;
          wv += waves_per_grid) {
         const uint64_t first = wv * span + lane;
         uint32_t s[128];
         const bool full = (wv + 1) * span <= nblocks;  // uniform across the wave
         if (full)
-            load_slices<false>(in, first, nblocks, s);
+            load_slices<false>(in, first, nblocks, s, tm);
         else
-            load_slices<true>(in, first, nblocks, s);
+            load_slices<true>(in, first, nblocks, s, tm);
         crypt_slices<NR, kDecrypt>(s, rk);
         if (full)
-            store_slices<false>(out, first, nblocks, s);
+            store_slices<false>(out, first, nblocks, s, tm);
         else
-            store_slices<true>(out, first, nblocks, s);
+            store_slices<true>(out, first, nblocks, s, tm);
     }
 }
 
