@@ -225,17 +225,6 @@ __device__ __forceinline__ uint32_t packed_addr(uint32_t w, uint32_t m3, uint32_
     return and_or(shl16<5>(x), m1f80, and_or(x, m3, base));
 }
 
-template <int PL>
-__device__ __forceinline__ void lookup4(uint32_t w, const uint32_t* lds, uint32_t m8, uint32_t m7,
-                                        const uint32_t base[4], uint32_t v[4])
-{
-    constexpr int S = PL == kPlace1 ? 128 : 256;
-    v[0] = lds_word(lds, addr_of<S, 0>(w, m8, m7, base[0]));
-    v[1] = lds_word(lds, addr_of<S, 1>(w, m8, m7, base[1]));
-    v[2] = lds_word(lds, addr_of<S, 2>(w, m8, m7, base[2]));
-    v[3] = lds_word(lds, addr_of<S, 3>(w, m8, m7, base[3]));
-}
-
 // One block through all rounds. K(i) returns round-key word i (uniform).
 template <int NR, bool kDecrypt, int PL, class K>
 __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
@@ -245,13 +234,21 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
     uint32_t w[4] = {in.x ^ key(0), in.y ^ key(1), in.z ^ key(2), in.w ^ key(3)};
 #pragma unroll
     for (int round = 1; round < NR; ++round) {
-        uint32_t v[4][4];  // v[j][t]: lookup with byte t of word j
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            lookup4<PL>(w[j], lds, lb.m8, lb.m7, lb.b, v[j]);
+        // v[j][t]: the lookup with byte t that output column j needs, issued
+        // column by column, so column j can be combined once its four lookups
+        // are back while the later columns' lookups are still in flight
+        uint32_t v[4][4];
+        constexpr int S = PL == kPlace1 ? 128 : 256;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t a = v[j][0], b = v[(j + s) & 3][1], c = v[(j + 2 * s) & 3][2], d = v[(j + 3 * s) & 3][3];
+            v[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m8, lb.m7, lb.b[0]));
+            v[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m8, lb.m7, lb.b[1]));
+            v[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m8, lb.m7, lb.b[2]));
+            v[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m8, lb.m7, lb.b[3]));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = v[j][0], b = v[j][1], c = v[j][2], d = v[j][3];
             const uint32_t k = key(4 * round + j);
             if (PL == kPlace4) {
                 w[j] = xor3_key(xor3(a, b, c), d, k);
@@ -266,13 +263,18 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
     }
     uint32_t o[4];
     if (!kDecrypt) {
-        uint32_t f[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            lookup4<PL>(w[j], lds, lb.m8, lb.m7, lb.f, f[j]);
+        uint32_t f[4][4];  // column by column, as in the inner rounds
+        constexpr int S = PL == kPlace1 ? 128 : 256;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t a = f[j][0], b = f[(j + s) & 3][1], c = f[(j + 2 * s) & 3][2], d = f[(j + 3 * s) & 3][3];
+            f[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m8, lb.m7, lb.f[0]));
+            f[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m8, lb.m7, lb.f[1]));
+            f[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m8, lb.m7, lb.f[2]));
+            f[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m8, lb.m7, lb.f[3]));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = f[j][0], b = f[j][1], c = f[j][2], d = f[j][3];
             uint32_t m;
             if (PL == kPlace1) {
                 // T0 = ({02}s, s, s, {03}s): take s from byte 1 for rows 0 and 1, byte 2 for rows 2 and 3
