@@ -351,7 +351,9 @@ def batched(torch, aes, inputs, bulk_rates):
     total = mix.total_blocks
     in_arena = inputs.device_random_bytes(2, 16 * total)
     out_arena = torch.empty_like(in_arena)
-    b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=1024)
+    # work-item size and blocks per thread from the autotune record (tuning/mi355x_sweep.json)
+    b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=4096,
+                      cfg=aes.BatchConfig(bpt=4))
     b.capture()
     b.replay()
     torch.cuda.synchronize()
@@ -379,7 +381,7 @@ def batched(torch, aes, inputs, bulk_rates):
     return {"messages": len(mix), "bytes": nbytes, "GB_s": round(batched_gbps, 1), "ms": round(ms, 3),
             "bulk_equivalent_GB_s": round(bulk_eq, 1), "vs_bulk": round(batched_gbps / bulk_eq, 4),
             "per_message_launch_GB_s": round(nbytes / per_msg_s / 1e9, 2),
-            "rejected_items": b.rejected_items(), "chunk_blocks": 1024, "graph": True}
+            "rejected_items": b.rejected_items(), "chunk_blocks": 4096, "bpt": 4, "graph": True}
 
 
 def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=None):

@@ -84,7 +84,7 @@ struct TuneEntry {
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
 // Compiled-in defaults from an MI355X autotune sweep (paper_1902_05234_amd.autotune,
-// variants timed in interleaved passes): small buffers are launch-bound and
+// variants timed in interleaved passes; record in tuning/mi355x_sweep.json): small buffers are launch-bound and
 // prefer the smallest table fill; up to 8 MiB the 2-table placement (two
 // 1024-thread workgroups per CU) wins; above that the 4-table placement with
 // 64 bytes per thread (32 for AES-192) is 4-5 % faster for every key size
