@@ -36,7 +36,8 @@ extern "C" {
 #define AES_OK 0
 #define AES_EINVAL (-1) /* bad argument: key size, Nr, null pointer, overlap */
 #define AES_EALIGN (-2) /* buffer not 16-byte aligned */
-#define AES_ENOMEM (-3) /* reserved: the library allocates nothing */
+#define AES_ENOMEM (-3) /* host memory for the serving engine's or pipe's bookkeeping ran out
+                            (no entry point allocates device memory) */
 #define AES_EHIP (-4)   /* HIP runtime or launch error */
 #define AES_EBUSY (-5)  /* reserved for callers' admission control */
 #define AES_ERANGE (-6) /* a count or capacity out of range */

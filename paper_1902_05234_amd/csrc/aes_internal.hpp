@@ -2,6 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <exception>
+#include <new>
+
+#include "../../include/aesgpu.h"
 
 namespace aesgpu {
 
@@ -83,5 +87,22 @@ int device_cu_count();
 // return code; fail_hip formats a HIP error.
 int fail(int code, const char* fmt, ...);
 int fail_hip(hipError_t e, const char* what);
+
+// Run an entry point's body and turn a C++ exception (a failed host
+// allocation, a thread that cannot be started) into a status code, so that
+// no exception crosses the C boundary.
+template <class F>
+int guarded(F&& body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(AES_ENOMEM, "out of host memory");
+    } catch (const std::exception& e) {
+        return fail(AES_EHIP, "internal error: %s", e.what());
+    } catch (...) {
+        return fail(AES_EHIP, "internal error");
+    }
+}
 
 }  // namespace aesgpu

@@ -84,9 +84,7 @@ int finish(Slot& s, uint8_t* host_out, bool staged)
 
 }  // namespace
 
-extern "C" {
-
-int aes_pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
+static int pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
 {
     if (out == nullptr || cfg == nullptr)
         return fail(AES_EINVAL, "null config or output pointer");
@@ -115,7 +113,12 @@ int aes_pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
     }
     p->chunk = cfg->chunk_bytes;
     p->has_pinned = cfg->pinned != nullptr;
-    p->slots.resize((size_t)cfg->nslots);
+    try {
+        p->slots.resize((size_t)cfg->nslots);
+    } catch (...) {
+        delete p;
+        throw;
+    }
     for (int i = 0; i < cfg->nslots; ++i) {
         Slot& s = p->slots[(size_t)i];
         s.dev = static_cast<uint8_t*>(cfg->dev) + (uint64_t)i * cfg->chunk_bytes;
@@ -131,7 +134,7 @@ int aes_pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
     return AES_OK;
 }
 
-int aes_pipe_destroy(aes_pipe* p)
+static int pipe_destroy(aes_pipe* p)
 {
     if (p == nullptr)
         return AES_OK;
@@ -146,8 +149,8 @@ int aes_pipe_destroy(aes_pipe* p)
     return AES_OK;
 }
 
-int aes_pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t* iv, const void* host_in,
-                 void* host_out, size_t nbytes, int flags)
+static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t* iv, const void* host_in,
+                    void* host_out, size_t nbytes, int flags)
 {
     if (p == nullptr)
         return fail(AES_EINVAL, "null pipe");
@@ -255,6 +258,24 @@ int aes_pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t*
     if (prev_dev != p->device)
         hipSetDevice(prev_dev);
     return rc;
+}
+
+extern "C" {
+
+int aes_pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
+{
+    return guarded([&] { return pipe_create(cfg, out); });
+}
+
+int aes_pipe_destroy(aes_pipe* p)
+{
+    return guarded([&] { return pipe_destroy(p); });
+}
+
+int aes_pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8_t* iv, const void* host_in,
+                 void* host_out, size_t nbytes, int flags)
+{
+    return guarded([&] { return pipe_run(p, op, rk, nr, iv, host_in, host_out, nbytes, flags); });
 }
 
 }  // extern "C"

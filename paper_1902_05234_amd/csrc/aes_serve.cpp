@@ -131,6 +131,7 @@ struct aes_server {
     int batches = 0;
     std::atomic<uint64_t> max_in_use{0};
     std::atomic<int> last_error{AES_OK};
+    std::atomic<bool> broken{false};       // the worker stopped on an internal failure
     std::atomic<uint64_t> arena_used_pub{0}, pending_pub{0};  // published by the worker for aes_server_stats
     std::atomic<uint64_t> submitted{0};                         // bumped by every submit and release
     std::thread worker;
@@ -214,7 +215,24 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
     return true;
 }
 
+void worker_loop(aes_server* s);
+
+// The worker thread: an exception (a failed host allocation) stops it and
+// marks the engine broken; submit and poll then report the failure.
 void worker_main(aes_server* s)
+{
+    try {
+        worker_loop(s);
+    } catch (const std::bad_alloc&) {
+        s->last_error.store(AES_ENOMEM);
+        s->broken.store(true);
+    } catch (...) {
+        s->last_error.store(AES_EHIP);
+        s->broken.store(true);
+    }
+}
+
+void worker_loop(aes_server* s)
 {
     if (!s->cfg.dry_run)
         hipSetDevice(s->device);
@@ -331,28 +349,29 @@ size_t aes_server_staging_bytes(const aes_serve_config* cfg)
     return (size_t)cfg->nslots * cfg->max_batch_items * sizeof(aes_work_item);
 }
 
-int aes_server_create(const aes_serve_config* cfg, const uint32_t* key_table_dev, size_t n_slots,
+static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_table_dev, size_t n_slots,
                       const void* in_pool, size_t in_blocks, void* out_arena, size_t out_blocks,
                       void* workspace_dev, size_t workspace_bytes, void* staging_host, size_t staging_bytes,
                       aes_server** out)
 {
     if (out == nullptr || cfg == nullptr)
-        return AES_EINVAL;
+        return fail(AES_EINVAL, "null config or output pointer");
     *out = nullptr;
     const aes_serve_config& c = *cfg;
     if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.max_batch_items == 0 || c.budget_bytes == 0 ||
         (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 || c.wg > 1024 || c.wg % 64)
-        return AES_EINVAL;
+        return fail(AES_EINVAL, "serve config out of range (nslots 1..16, chunk/items/budget > 0, bpt 1/2/4, "
+                                "wg multiple of 64 in [64, 1024])");
     if (!c.dry_run && (key_table_dev == nullptr || in_pool == nullptr || out_arena == nullptr ||
                        workspace_dev == nullptr || staging_host == nullptr))
-        return AES_EINVAL;
+        return fail(AES_EINVAL, "null key table, input pool, output arena, workspace or staging");
     if (workspace_bytes < aes_server_workspace_bytes(cfg) || staging_bytes < aes_server_staging_bytes(cfg))
-        return AES_ERANGE;
+        return fail(AES_ERANGE, "workspace or staging smaller than aes_server_workspace_bytes/staging_bytes");
     if (n_slots == 0 || out_blocks == 0)
-        return AES_EINVAL;
+        return fail(AES_EINVAL, "empty key table or output arena");
     aes_server* s = new (std::nothrow) aes_server();
     if (!s)
-        return AES_ENOMEM;
+        return fail(AES_ENOMEM, "out of host memory");
     s->cfg = c;
     s->key_table = key_table_dev;
     s->n_slots = n_slots;
@@ -360,8 +379,13 @@ int aes_server_create(const aes_serve_config* cfg, const uint32_t* key_table_dev
     s->in_blocks = in_blocks;
     s->out_arena = out_arena;
     s->out_blocks = out_blocks;
-    s->arena = Arena(out_blocks);
-    s->slots.resize(c.nslots);
+    try {
+        s->arena = Arena(out_blocks);
+        s->slots.resize(c.nslots);
+    } catch (...) {
+        delete s;
+        throw;
+    }
     const size_t items_bytes = ((size_t)c.max_batch_items * sizeof(aes_work_item) + 255) & ~(size_t)255;
     int rc = AES_OK;
     if (!c.dry_run) {
@@ -399,15 +423,26 @@ int aes_server_create(const aes_serve_config* cfg, const uint32_t* key_table_dev
         return rc;
     }
     s->t0 = Clock::now();
-    s->worker = std::thread(worker_main, s);
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        for (Slot& sl : s->slots) {
+            if (sl.event) hipEventDestroy(sl.event);
+            if (sl.stream) hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        throw;
+    }
     *out = s;
     return AES_OK;
 }
 
-int aes_server_submit(aes_server* s, const aes_request* reqs, size_t n, uint64_t* first_id)
+static int server_submit_impl(aes_server* s, const aes_request* reqs, size_t n, uint64_t* first_id)
 {
     if (s == nullptr || (n > 0 && reqs == nullptr))
         return AES_EINVAL;
+    if (s->broken.load())
+        return AES_EHIP;
     std::vector<Req*> made;
     made.reserve(n);
     const double t = s->now();
@@ -441,7 +476,7 @@ int aes_server_submit(aes_server* s, const aes_request* reqs, size_t n, uint64_t
     return AES_OK;
 }
 
-int aes_server_poll(aes_server* s, aes_served* out, size_t cap, size_t* n)
+static int server_poll_impl(aes_server* s, aes_served* out, size_t cap, size_t* n)
 {
     if (s == nullptr || n == nullptr || (cap > 0 && out == nullptr))
         return AES_EINVAL;
@@ -465,10 +500,12 @@ int aes_server_poll(aes_server* s, aes_served* out, size_t cap, size_t* n)
         delete q;
     }
     *n = take.size();
+    if (s->broken.load())
+        return s->last_error.load() == AES_ENOMEM ? AES_ENOMEM : AES_EHIP;
     return s->last_error.exchange(AES_OK) == AES_OK ? AES_OK : AES_EHIP;
 }
 
-int aes_server_release(aes_server* s, const aes_served* done, size_t n)
+static int server_release_impl(aes_server* s, const aes_served* done, size_t n)
 {
     if (s == nullptr || (n > 0 && done == nullptr))
         return AES_EINVAL;
@@ -485,7 +522,7 @@ int aes_server_release(aes_server* s, const aes_served* done, size_t n)
     return AES_OK;
 }
 
-int aes_server_stats(aes_server* s, aes_serve_stats* st)
+static int server_stats_impl(aes_server* s, aes_serve_stats* st)
 {
     if (s == nullptr || st == nullptr)
         return AES_EINVAL;
@@ -497,7 +534,7 @@ int aes_server_stats(aes_server* s, aes_serve_stats* st)
     return AES_OK;
 }
 
-int aes_server_destroy(aes_server* s)
+static int server_destroy_impl(aes_server* s)
 {
     if (s == nullptr)
         return AES_OK;
@@ -517,11 +554,15 @@ int aes_server_destroy(aes_server* s)
     }
     for (Req* q : s->completed)
         delete q;
+    for (Req* q : s->incoming)  // non-empty only if the worker stopped on a failure
+        delete q;
+    for (Req* q : s->pending)
+        delete q;
     delete s;
     return AES_OK;
 }
 
-int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arrival_s, size_t n, aes_served* results)
+static int serve_replay_impl(aes_server* s, const aes_request* reqs, const double* arrival_s, size_t n, aes_served* results)
 {
     if (s == nullptr || (n > 0 && (reqs == nullptr || arrival_s == nullptr || results == nullptr)))
         return AES_EINVAL;
@@ -540,7 +581,7 @@ int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arriv
             ++k;
         if (k > next) {
             uint64_t fid;
-            int r = aes_server_submit(s, reqs + next, k - next, &fid);
+            int r = server_submit_impl(s, reqs + next, k - next, &fid);
             if (r != AES_OK)
                 return r;
             if (!have_id0) {
@@ -550,9 +591,11 @@ int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arriv
             next = k;
         }
         size_t m = 0;
-        int pr = aes_server_poll(s, buf.data(), buf.size(), &m);
+        int pr = server_poll_impl(s, buf.data(), buf.size(), &m);
         if (pr != AES_OK)
             rc = pr;
+        if (s->broken.load())
+            return rc;
         for (size_t i = 0; i < m; ++i) {
             const size_t idx = (size_t)(buf[i].id - id0);
             if (idx < n) {
@@ -569,6 +612,47 @@ int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arriv
         }
     }
     return rc;
+}
+
+int aes_server_create(const aes_serve_config* cfg, const uint32_t* key_table_dev, size_t n_slots,
+                      const void* in_pool, size_t in_blocks, void* out_arena, size_t out_blocks,
+                      void* workspace_dev, size_t workspace_bytes, void* staging_host, size_t staging_bytes,
+                      aes_server** out)
+{
+    return guarded([&] {
+        return server_create_impl(cfg, key_table_dev, n_slots, in_pool, in_blocks, out_arena, out_blocks,
+                                  workspace_dev, workspace_bytes, staging_host, staging_bytes, out);
+    });
+}
+
+int aes_server_submit(aes_server* s, const aes_request* reqs, size_t n, uint64_t* first_id)
+{
+    return guarded([&] { return server_submit_impl(s, reqs, n, first_id); });
+}
+
+int aes_server_poll(aes_server* s, aes_served* out, size_t cap, size_t* n)
+{
+    return guarded([&] { return server_poll_impl(s, out, cap, n); });
+}
+
+int aes_server_release(aes_server* s, const aes_served* done, size_t n)
+{
+    return guarded([&] { return server_release_impl(s, done, n); });
+}
+
+int aes_server_stats(aes_server* s, aes_serve_stats* st)
+{
+    return guarded([&] { return server_stats_impl(s, st); });
+}
+
+int aes_server_destroy(aes_server* s)
+{
+    return guarded([&] { return server_destroy_impl(s); });
+}
+
+int aes_serve_replay(aes_server* s, const aes_request* reqs, const double* arrival_s, size_t n, aes_served* results)
+{
+    return guarded([&] { return serve_replay_impl(s, reqs, arrival_s, n, results); });
 }
 
 }  // extern "C"
