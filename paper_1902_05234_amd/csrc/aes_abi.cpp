@@ -75,7 +75,8 @@ int size_bucket(uint64_t nblocks)
     if (nblocks <= 4096) return 1;
     if (nblocks <= 65536) return 2;
     if (nblocks <= 524288) return 3;
-    return 4;
+    if (nblocks <= 2097152) return 4;
+    return 5;
 }
 
 struct TuneEntry {
@@ -83,12 +84,13 @@ struct TuneEntry {
 };
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
-// Compiled-in defaults from an MI355X autotune sweep (paper_1902_05234_amd.autotune,
-// variants timed in interleaved passes; record in tuning/mi355x_sweep.json): small buffers are launch-bound and
-// prefer the smallest table fill; up to 8 MiB the 2-table placement (two
-// 1024-thread workgroups per CU) wins; above that the 4-table placement with
-// 64 bytes per thread (32 for AES-192) is 4-5 % faster for every key size
-// and both directions.
+// Compiled-in defaults from MI355X autotune sweeps (paper_1902_05234_amd.autotune,
+// variants timed in interleaved passes; record in tuning/mi355x_sweep.json,
+// mid sizes timed with graph replays): small buffers are launch-bound and
+// prefer the smallest table fill; up to 32 MiB the 2-table placement (two
+// 1024-thread workgroups per CU, half the fill per workgroup) wins; above
+// that the 4-table placement with 64 bytes per thread is 4-8 % faster for
+// every key size and both directions.
 struct TuneDefaults {
     static void set(TuneEntry& t, int bpt, int wg, int placement)
     {
@@ -103,9 +105,9 @@ struct TuneDefaults {
                 for (int b = 0; b < 3; ++b)
                     set(g_tune[n][d][b], 1, 512, AES_PLACEMENT_TTABLE1);
                 set(g_tune[n][d][3], 2, 1024, AES_PLACEMENT_TTABLE2);
+                set(g_tune[n][d][4], 2, 1024, AES_PLACEMENT_TTABLE2);
+                set(g_tune[n][d][5], 4, 1024, AES_PLACEMENT_TTABLE4);
             }
-            set(g_tune[n][0][4], n == 1 ? 2 : 4, 1024, AES_PLACEMENT_TTABLE4);
-            set(g_tune[n][1][4], n == 1 ? 2 : 4, 1024, AES_PLACEMENT_TTABLE4);
         }
     }
 } g_tune_defaults;
