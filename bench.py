@@ -193,6 +193,30 @@ def roofline(b, traffic, aes):
     }
 
 
+def openssl_context(cores):
+    """`openssl speed` for AES-128-ECB on 16 KiB buffers (AES-NI), one thread and
+    all host threads: a labelled fast-CPU context line, not the baseline."""
+    import subprocess
+    out = {}
+    for label, extra in (("one_thread", []), ("all_threads", ["-multi", str(cores)])):
+        try:
+            r = subprocess.run(["openssl", "speed"] + extra + ["-evp", "aes-128-ecb", "-bytes", "16384", "-seconds", "1"],
+                               capture_output=True, text=True, timeout=60)
+        except (OSError, subprocess.TimeoutExpired):
+            return None
+        rate = None
+        for line in r.stdout.splitlines():
+            parts = line.split()
+            if len(parts) == 2 and parts[0] in ("AES-128-ECB", "evp") and parts[1].endswith("k"):
+                rate = float(parts[1][:-1]) * 1e3
+        if rate is None:
+            return None
+        out[label + "_GB_s"] = round(rate / 1e9, 3)
+    out["threads"] = cores
+    out["what"] = "openssl speed -evp aes-128-ecb -bytes 16384 (AES-NI; context, not the oracle baseline)"
+    return out
+
+
 def cpu_baseline(b, args):
     import numpy as np
 
@@ -227,6 +251,7 @@ def cpu_baseline(b, args):
             "sample": "AES-128 ECB encrypt then decrypt of the first %d MiB of the 1 GiB workload" % (nbytes // MiB),
             "seconds": round(dt, 2), "cpu_model": model or platform.processor(),
             "one_thread_encrypt_MB_s": round(one_thread, 2),
+            "openssl_context": openssl_context(cores),
             "matches_gpu_on_sample": gpu_match}
 
 
