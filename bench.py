@@ -217,6 +217,37 @@ def openssl_context(cores):
     return out
 
 
+def measured_roofs(torch, aes, inputs):
+    """The probes of the roofs: a 1 GiB device copy (HBM), conflict-free LDS
+    lookups at 32 waves per CU, full-rate VALU chains; median of 5 timed
+    launches each."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    scratch = torch.empty(cus * 2048, dtype=torch.int32, device="cuda")
+    res = {}
+    for name, which, iters in (("lds", aes.AES_PROBE_LDS, 20000), ("valu", aes.AES_PROBE_VALU, 20000)):
+        work = aes.aes_roof_probe(which, 10, scratch)
+        tm = Timer(torch)
+        for _ in range(5):
+            tm.run(lambda: aes.aes_roof_probe(which, iters, scratch))
+        ms = sorted(tm.ms())[2]
+        work = aes.aes_roof_probe(which, iters, scratch)
+        res[name] = work / (ms * 1e-3)
+    x = inputs.device_random_bytes(8, GiB)
+    y = torch.empty_like(x)
+    aes.aes_device_copy(x, y)
+    tm = Timer(torch)
+    for _ in range(5):
+        tm.run(lambda: aes.aes_device_copy(x, y))
+    ms = sorted(tm.ms())[2]
+    del x, y
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GB_s": round(2 * GiB / (ms * 1e-3) / 1e9, 1),
+            "lds_Glookup_s": round(res["lds"] / 1e9, 1),
+            "valu_Tlane_op_s": round(res["valu"] / 1e12, 2),
+            "what": "1 GiB device copy (read + write bytes); conflict-free ds_read_b32 with random per-lane "
+                    "entries, 32 waves/CU; independent v_bitop3_b32 chains, 32 waves/CU"}
+
+
 def cpu_baseline(b, args):
     import numpy as np
 
@@ -560,9 +591,16 @@ def main():
         "enc_GB_s": round(b["nbytes"] / (sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3) / 1e9, 1),
         "dec_GB_s": round(b["nbytes"] / (sum(b["dec_ms"]) / len(b["dec_ms"]) * 1e-3) / 1e9, 1),
         "roofline": roofline(b, traffic, aes),
+        "measured_roofs": None,
         "kernel_source_hash": kernel_source_hash(),
         "device": props.name,
     }
+    roofs = measured_roofs(torch, aes, inputs)
+    result["measured_roofs"] = roofs
+    rl = result["roofline"]
+    rl["measured_peak"] = roofs["lds_Glookup_s"]
+    rl["frac_of_measured"] = round(rl["achieved"] / roofs["lds_Glookup_s"], 4)
+    log("measured roofs:", roofs)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(b, args)
         log("cpu baseline done")

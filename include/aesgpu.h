@@ -156,6 +156,24 @@ int aes_cbc_decrypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, const
                             const aes_variant *variant, void *stream);
 
 /*
+ * aes_roof_probe -- the measured roofs beside the published ones.
+ *   which = AES_PROBE_LDS:  conflict-free ds_read_b32 lookups with per-lane
+ *           random entries in a 32-replica table laid out like the T-tables,
+ *           32 waves per CU (the cipher's binding unit);
+ *   which = AES_PROBE_VALU: independent full-rate v_bitop3_b32 chains, 32
+ *           waves per CU.
+ *   iters:  loop count in [1, 2^24]; each thread does 16 operations per loop.
+ *   out_dev, out_bytes: device scratch of one 32-bit word per probe thread
+ *           (compute units x 2048 threads), written with a checksum.
+ *   work:   if not NULL, receives the number of lookups / lane-operations
+ *           the launch performs; the caller times the launch on stream.
+ * The copy roof is aes_device_copy.  Diagnostic only; asynchronous.
+ */
+#define AES_PROBE_LDS 0
+#define AES_PROBE_VALU 1
+int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, uint64_t *work, void *stream);
+
+/*
  * Host-inclusive path (aes_pipe_*): host buffer in, host buffer out.  The
  * paper's GPU timings are of files in host memory (section 5, Tables 4-5),
  * i.e. they include the copies over the host link; this path measures and

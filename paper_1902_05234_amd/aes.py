@@ -100,6 +100,7 @@ def _lib() -> ctypes.CDLL:
                 "aes_ecb_batch": ([_c_p, _c_sz, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
                                    ctypes.POINTER(_BatchConfig), _c_p], _c_i),
                 "aes_device_copy": ([_c_p, _c_p, _c_sz, _c_p], _c_i),
+                "aes_roof_probe": ([_c_i, ctypes.c_uint32, _c_p, _c_sz, ctypes.POINTER(ctypes.c_uint64), _c_p], _c_i),
                 "aes_host_tables": ([_u8p, _u8p, _u32p, _u32p], _c_i),
             }
             for name, (args, res) in sig.items():
@@ -115,7 +116,7 @@ def exported_symbols():
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
             "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
             "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
-            "aes_ecb_batch", "aes_device_copy", "aes_host_tables", "aes_server_workspace_bytes",
+            "aes_ecb_batch", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
             "aes_pipe_destroy", "aes_pipe_run"]
@@ -368,6 +369,19 @@ def aes_ecb_batch(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out
 def aes_device_copy(inp, out, nbytes: int | None = None, stream=None):
     nbytes = inp.numel() * inp.element_size() if nbytes is None else int(nbytes)
     _check(_lib().aes_device_copy(inp.data_ptr(), out.data_ptr(), nbytes, _stream_handle(stream)))
+
+
+AES_PROBE_LDS = 0
+AES_PROBE_VALU = 1
+
+
+def aes_roof_probe(which: int, iters: int, out, stream=None) -> int:
+    """Launch a roofline probe (AES_PROBE_LDS / AES_PROBE_VALU) writing into the
+    device tensor ``out``; returns the operations it performs (time it with events)."""
+    work = ctypes.c_uint64(0)
+    _check(_lib().aes_roof_probe(int(which), int(iters), out.data_ptr(), out.numel() * out.element_size(),
+                                 ctypes.byref(work), _stream_handle(stream)))
+    return work.value
 
 
 def aes_host_tables():

@@ -535,6 +535,31 @@ int aes_host_tables(uint8_t* sbox, uint8_t* inv_sbox, uint32_t* te0, uint32_t* t
     return AES_OK;
 }
 
+int aes_roof_probe(int which, uint32_t iters, void* out_dev, size_t out_bytes, uint64_t* work, void* stream)
+{
+    if (which != AES_PROBE_LDS && which != AES_PROBE_VALU)
+        return fail(AES_EINVAL, "unknown probe %d", which);
+    if (iters == 0 || iters > (1u << 24))
+        return fail(AES_EINVAL, "iters must be in [1, 2^24], got %u", iters);
+    if (out_dev == nullptr)
+        return fail(AES_EINVAL, "null probe output");
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    const uint64_t threads = (uint64_t)cus * 2u * 1024u;
+    if (out_dev == nullptr || out_bytes < threads * 4u)
+        return fail(AES_EINVAL, "out_dev must hold %llu bytes (one word per probe thread)",
+                    (unsigned long long)(threads * 4u));
+    if (reinterpret_cast<uintptr_t>(out_dev) & 3u)
+        return fail(AES_EALIGN, "out_dev must be 4-byte aligned");
+    if (work != nullptr)
+        *work = threads * 16u * iters;  // lookups or VALU lane-operations
+    hipError_t e = launch_probe(which, static_cast<uint32_t*>(out_dev), iters, cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "probe launch");
+    return AES_OK;
+}
+
 int aes_device_copy(const void* in, void* out, size_t nbytes, void* stream)
 {
     if (nbytes == 0)

@@ -27,6 +27,10 @@ hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decr
 
 hipError_t launch_copy(const void* in, void* out, uint64_t n16, int grid, hipStream_t stream);
 
+// Roofline probes (aes_microbench.hip): which 0 = LDS lookups, 1 = VALU;
+// cus * 2 workgroups of 1024 threads, one output word per thread.
+hipError_t launch_probe(int which, uint32_t* out, uint32_t iters, int cus, hipStream_t stream);
+
 // Bitsliced placement (no tables): 32 blocks per lane, workgroups of at most
 // kBitsliceMaxWg threads (the slices take most of the register file).
 constexpr int kBitsliceMaxWg = 256;

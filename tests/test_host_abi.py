@@ -266,6 +266,15 @@ def test_pipe_config_checks_before_any_device_call():
     assert lib.aes_pipe_run(None, 0, rk, 10, None, A, A, 16, 0) == aes.AES_EINVAL
 
 
+def test_roof_probe_checks_before_any_device_call():
+    lib = aes._lib()
+    w = aes.ctypes.c_uint64(0)
+    assert lib.aes_roof_probe(7, 10, 0x10000, 1 << 24, aes.ctypes.byref(w), None) == aes.AES_EINVAL
+    assert lib.aes_roof_probe(aes.AES_PROBE_LDS, 0, 0x10000, 1 << 24, aes.ctypes.byref(w), None) == aes.AES_EINVAL
+    assert lib.aes_roof_probe(aes.AES_PROBE_VALU, (1 << 24) + 1, 0x10000, 1 << 24, None, None) == aes.AES_EINVAL
+    assert lib.aes_roof_probe(aes.AES_PROBE_LDS, 10, None, 1 << 24, None, None) == aes.AES_EINVAL
+
+
 def test_tuning_table_round_trip():
     for nr in (10, 12, 14):
         for dec in (False, True):
