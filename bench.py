@@ -33,6 +33,7 @@ few bulk and copy launches (for rocprofv3).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -107,16 +108,21 @@ def read_traffic(nbytes_payload: int, instance: str):
 
 
 class Timer:
-    """HIP events on the stream the kernels are launched on."""
+    """HIP events on the stream the kernels are launched on.  `prepare` pairs
+    are created up front, so a timed loop of that many launches only records
+    them; further pairs are created as needed."""
 
-    def __init__(self, torch):
+    def __init__(self, torch, prepare=0):
         self.torch = torch
+        self.free = [self._pair() for _ in range(prepare)]
         self.pairs = []
+
+    def _pair(self):
+        return self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True)
 
     def run(self, fn):
         s = self.torch.cuda.current_stream()
-        a = self.torch.cuda.Event(enable_timing=True)
-        b = self.torch.cuda.Event(enable_timing=True)
+        a, b = self.free.pop() if self.free else self._pair()
         a.record(s)
         fn()
         b.record(s)
@@ -133,7 +139,7 @@ def bulk(torch, aes, inputs, args):
     x = inputs.device_random_bytes(1, nbytes)
     c = torch.empty_like(x)
     p = torch.empty_like(x)
-    t_enc, t_dec = Timer(torch), Timer(torch)
+    t_enc, t_dec = Timer(torch, args.steps), Timer(torch, args.steps)
 
     def step(timed: bool):
         ks = aes.aes_expand_key(key)
@@ -146,15 +152,21 @@ def bulk(torch, aes, inputs, args):
 
     for _ in range(args.warmup):
         step(False)
+    # The timed steps follow the warm-up directly: an idle gap would let the
+    # engine clock settle again and the first timed launches would pay its
+    # ramp.  The round trip is checked on the output of the timed steps.
     torch.cuda.synchronize()
+    gc.disable()  # no collector pause between launches inside the timed region
+    try:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    finally:
+        gc.enable()
     if not torch.equal(p, x):
         raise RuntimeError("round trip failed on the 1 GiB buffer")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
     enc_ms, dec_ms = t_enc.ms(), t_dec.ms()
     return dict(key=key, x=x, c=c, nbytes=nbytes, elapsed=elapsed, enc_ms=enc_ms, dec_ms=dec_ms)
 
@@ -290,11 +302,24 @@ GRAPH_TIMED_MAX = 64 * MiB   # up to this size the host's per-call cost would do
 GRAPH_LAUNCHES = 20
 
 
+WARM_SECONDS = 0.05  # the engine clock takes a few tens of ms of load to ramp up from idle
+
+
+def warm(torch, fn):
+    """Run fn back to back for WARM_SECONDS before a timing."""
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= WARM_SECONDS:
+            return
+
+
 def launch_ms(torch, fn, n):
-    """Device time of one launch of fn on an n-byte buffer.  Small buffers: 20
-    launches captured in a HIP graph, replayed 5 times (median replay / 20),
-    so the host's per-call cost stays out of the figure; large buffers: HIP
-    events around single eager launches (median)."""
+    """Device time of one launch of fn on an n-byte buffer, after a warm-up.
+    Small buffers: 20 launches captured in a HIP graph, replayed 5 times
+    (median replay / 20), so the host's per-call cost stays out of the figure;
+    large buffers: HIP events around single eager launches (median)."""
     fn()
     torch.cuda.synchronize()
     if n <= GRAPH_TIMED_MAX:
@@ -302,14 +327,15 @@ def launch_ms(torch, fn, n):
         with torch.cuda.graph(g):
             for _ in range(GRAPH_LAUNCHES):
                 fn()
-        g.replay()
+        warm(torch, g.replay)
         tm = Timer(torch)
         for _ in range(5):
             tm.run(g.replay)
         ms = sorted(tm.ms())[2] / GRAPH_LAUNCHES
         del g
         return ms
-    reps = max(3, min(50, int(4 * GiB / n)))
+    warm(torch, fn)
+    reps = max(5, min(50, int(8 * GiB / n)))
     tm = Timer(torch)
     for _ in range(reps):
         tm.run(fn)
@@ -329,36 +355,31 @@ def sweep(torch, aes, inputs, sizes):
                      (lambda: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xi, xo))
                 ms = launch_ms(torch, fn, n)
                 out["aes%d_%s_%s" % (keybits, "dec" if dec else "enc", size_name(n))] = round(n / (ms * 1e-3) / 1e9, 1)
-    # structured control: in an all-zero buffer every block is the same, so
-    # every lane reads the same table entry in every round (LDS broadcast);
-    # random data spreads the lanes over the 32 replicas
     ks = aes.aes_expand_key(inputs.random_key(3, 128))
     n = min(GiB, max(sizes))
     xi, xo = buf_in[:n], buf_out[:n]
-    xi.zero_()
-    fn = lambda: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xi, xo)
-    fn()
-    tm = Timer(torch)
-    for _ in range(10):
-        tm.run(fn)
-    ms = sorted(tm.ms())[5]
-    out["aes128_enc_%s_all_zero" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+
+    def timed10(fn):
+        warm(torch, fn)
+        tm = Timer(torch)
+        for _ in range(10):
+            tm.run(fn)
+        return sorted(tm.ms())[5]
+
     # counter mode: same round core; the lookups depend on the counters only
-    fn = lambda: aes.aes_ctr_crypt(ks.rk_enc, ks.nr, bytes(range(16)), 0, xi, xo)
-    fn()
-    tm = Timer(torch)
-    for _ in range(10):
-        tm.run(fn)
-    ms = sorted(tm.ms())[5]
+    ms = timed10(lambda: aes.aes_ctr_crypt(ks.rk_enc, ks.nr, bytes(range(16)), 0, xi, xo))
     out["aes128_ctr_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
-    # CBC decryption: ECB decryption plus the XOR of the preceding ciphertext block
-    fn = lambda: aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, bytes(16), xi, xo)
-    fn()
-    tm = Timer(torch)
-    for _ in range(10):
-        tm.run(fn)
-    ms = sorted(tm.ms())[5]
+    # CBC decryption (random ciphertext): ECB decryption plus the XOR of the
+    # preceding ciphertext block
+    ms = timed10(lambda: aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, bytes(16), xi, xo))
     out["aes128_cbc_dec_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    # structured control, last because it overwrites the input: in an
+    # all-zero buffer every block is the same, so every lane reads the same
+    # table entry in every round (LDS broadcast); random data spreads the
+    # lanes over the 32 replicas
+    xi.zero_()
+    ms = timed10(lambda: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xi, xo))
+    out["aes128_enc_%s_all_zero" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
     del buf_in, buf_out
     torch.cuda.empty_cache()
     return out
@@ -437,8 +458,7 @@ def batched(torch, aes, inputs, bulk_rates):
     b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=4096,
                       cfg=aes.BatchConfig(bpt=4))
     b.capture()
-    b.replay()
-    torch.cuda.synchronize()
+    warm(torch, b.replay)
     tm = Timer(torch)
     for _ in range(5):
         tm.run(b.replay)
@@ -525,8 +545,8 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
