@@ -31,11 +31,13 @@
 // ((e >> 2) * 128 + r * 4 + (e & 3), 8 KiB) with 1 or 2 tables.
 //
 // Lookup addresses put the state byte into bits 8..15 (stride 256) or 7..14
-// (stride 128) and OR in the lane's base, using the VALU forms gfx950 issues
-// at full rate (v_bitop3_b32 with VGPR operands, v_lshlrev_b16,
-// v_lshrrev_b32, v_or_b32).  v_perm_b32, v_bfe_u32, v_and_or_b32, SDWA forms
-// and any form with an SGPR operand issue at about half that rate, which is
-// why the address code is written with inline v_bitop3_b32 / v_lshlrev_b16.
+// (stride 128) and combine it with the lane's base.  With stride 256 that is
+// one v_perm_b32 per lookup, and the last round merges its four bytes with
+// two more.  A byte permute issues at about half the rate of a plain
+// v_bitop3_b32, so in instruction slots it costs what the two-instruction
+// shift-and-OR form costs; but the kernel runs at the board power limit,
+// where fewer instructions (and fewer VGPR reads: the selectors stay in
+// SGPRs) mean less energy per block and a higher engine clock.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -65,6 +67,11 @@ static __constant__ TableSet c_tables = make_tables();
 __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t m, uint32_t b)
 {
     return __builtin_amdgcn_bitop3_b32(a, m, b, 0xea);  // (a & m) | b
+}
+
+__device__ __forceinline__ uint32_t or_xor(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x56);  // (a | b) ^ c
 }
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
@@ -106,7 +113,7 @@ struct LaneBases {
     uint32_t b[4];   // base used for state byte t in an inner round
     uint32_t f[4];   // base used for state byte t in the last (encryption) round
     uint32_t bs;     // InvS base
-    uint32_t m8, m7, m16, m24, m3, m1f80;
+    uint32_t m7, m3, m1f80;
 
     __device__ __forceinline__ explicit LaneBases(uint32_t lane)
     {
@@ -127,10 +134,7 @@ struct LaneBases {
         }
         bs = Layout<PL, kDecrypt>::si_offset | r4;
         // opaque copies keep the masks in VGPRs so every bitop3 operand is a VGPR
-        asm volatile("v_mov_b32 %0, 0xff00" : "=v"(m8));
         asm volatile("v_mov_b32 %0, 0x7f80" : "=v"(m7));
-        asm volatile("v_mov_b32 %0, 0xff0000" : "=v"(m16));
-        asm volatile("v_mov_b32 %0, 0xff000000" : "=v"(m24));
         asm volatile("v_mov_b32 %0, 3" : "=v"(m3));
         asm volatile("v_mov_b32 %0, 0x1f80" : "=v"(m1f80));
     }
@@ -200,21 +204,30 @@ __device__ __forceinline__ void fill_tables(uint32_t* lds, const TableSet* __res
     }
 }
 
-// Address of byte t of w in a table with entry stride 256 or 128.
+// Address of byte t of w in a table with entry stride 256 or 128.  Stride
+// 256: one v_perm_b32 writes byte t of w into bits 8..15 and copies bytes 0
+// and 2 of the lane's base (bytes 1 and 3 of every base are zero).  The
+// selector is uniform and stays in an SGPR.  Stride 128 needs a 7-bit shift,
+// which a byte permute cannot do.
 template <int STRIDE, int T>
-__device__ __forceinline__ uint32_t addr_of(uint32_t w, uint32_t m8, uint32_t m7, uint32_t base)
+__device__ __forceinline__ uint32_t addr_of(uint32_t w, uint32_t m7, uint32_t base)
 {
     if (STRIDE == 256) {
-        if (T == 0) return shl16<8>(w) | base;
-        if (T == 1) return and_or(w, m8, base);
-        if (T == 2) return and_or(w >> 8, m8, base);
-        return and_or(w >> 16, m8, base);
+        return __builtin_amdgcn_perm(w, base, 0x0c020000u | ((4u + T) << 8));
     } else {
         if (T == 0) return and_or(shl16<7>(w), m7, base);
         if (T == 1) return and_or(w >> 1, m7, base);
         if (T == 2) return and_or(w >> 9, m7, base);
         return and_or(w >> 17, m7, base);
     }
+}
+
+// Bytes 0 and 1 of the result from (a, b), bytes 2 and 3 from (c, d): one
+// v_perm_b32 per pair, selectors chosen by the caller; then XOR the key.
+__device__ __forceinline__ uint32_t merge4(uint32_t a, uint32_t b, uint32_t sel_ab, uint32_t c, uint32_t d,
+                                           uint32_t sel_cd, uint32_t k)
+{
+    return or_xor(__builtin_amdgcn_perm(b, a, sel_ab), __builtin_amdgcn_perm(d, c, sel_cd), k);
 }
 
 // Address of byte t of w in the byte-packed InvS table.
@@ -241,10 +254,10 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
         constexpr int S = PL == kPlace1 ? 128 : 256;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            v[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m8, lb.m7, lb.b[0]));
-            v[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m8, lb.m7, lb.b[1]));
-            v[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m8, lb.m7, lb.b[2]));
-            v[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m8, lb.m7, lb.b[3]));
+            v[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m7, lb.b[0]));
+            v[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m7, lb.b[1]));
+            v[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m7, lb.b[2]));
+            v[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m7, lb.b[3]));
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -267,46 +280,34 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
         constexpr int S = PL == kPlace1 ? 128 : 256;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            f[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m8, lb.m7, lb.f[0]));
-            f[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m8, lb.m7, lb.f[1]));
-            f[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m8, lb.m7, lb.f[2]));
-            f[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m8, lb.m7, lb.f[3]));
+            f[j][0] = lds_word(lds, addr_of<S, 0>(w[j], lb.m7, lb.f[0]));
+            f[j][1] = lds_word(lds, addr_of<S, 1>(w[(j + s) & 3], lb.m7, lb.f[1]));
+            f[j][2] = lds_word(lds, addr_of<S, 2>(w[(j + 2 * s) & 3], lb.m7, lb.f[2]));
+            f[j][3] = lds_word(lds, addr_of<S, 3>(w[(j + 3 * s) & 3], lb.m7, lb.f[3]));
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t a = f[j][0], b = f[j][1], c = f[j][2], d = f[j][3];
-            uint32_t m;
-            if (PL == kPlace1) {
-                // T0 = ({02}s, s, s, {03}s): take s from byte 1 for rows 0 and 1, byte 2 for rows 2 and 3
-                m = (a >> 8) & 0xffu;
-                m = and_or(b, lb.m8, m);
-                m = and_or(c, lb.m16, m);
-                m = and_or(d << 8, lb.m24, m);
-            } else {
-                m = a & 0xffu;
-                m = and_or(b, lb.m8, m);
-                m = and_or(c, lb.m16, m);
-                m = and_or(d, lb.m24, m);
-            }
-            o[j] = m ^ key(4 * NR + j);
+            // byte t of the output is byte t of f[j][t] (PL1: byte 1 for
+            // rows 0 and 1, byte 2 for rows 2 and 3, T0 being ({02}s, s, s, {03}s))
+            if (PL == kPlace1)
+                o[j] = merge4(f[j][0], f[j][1], 0x0c0c0501u, f[j][2], f[j][3], 0x06020c0cu, key(4 * NR + j));
+            else
+                o[j] = merge4(f[j][0], f[j][1], 0x0c0c0500u, f[j][2], f[j][3], 0x07020c0cu, key(4 * NR + j));
         }
     } else if (PL == kPlace4) {
         uint32_t f[4][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t bs[4] = {lb.bs, lb.bs, lb.bs, lb.bs};
-            f[j][0] = lds_word(lds, addr_of<128, 0>(w[j], lb.m8, lb.m7, bs[0]));
-            f[j][1] = lds_word(lds, addr_of<128, 1>(w[j], lb.m8, lb.m7, bs[1]));
-            f[j][2] = lds_word(lds, addr_of<128, 2>(w[j], lb.m8, lb.m7, bs[2]));
-            f[j][3] = lds_word(lds, addr_of<128, 3>(w[j], lb.m8, lb.m7, bs[3]));
+            f[j][0] = lds_word(lds, addr_of<128, 0>(w[j], lb.m7, bs[0]));
+            f[j][1] = lds_word(lds, addr_of<128, 1>(w[j], lb.m7, bs[1]));
+            f[j][2] = lds_word(lds, addr_of<128, 2>(w[j], lb.m7, bs[2]));
+            f[j][3] = lds_word(lds, addr_of<128, 3>(w[j], lb.m7, bs[3]));
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            uint32_t m = f[j][0] & 0xffu;
-            m = and_or(f[(j + s) & 3][1], lb.m8, m);
-            m = and_or(f[(j + 2 * s) & 3][2], lb.m16, m);
-            m = and_or(f[(j + 3 * s) & 3][3], lb.m24, m);
-            o[j] = m ^ key(4 * NR + j);
+            o[j] = merge4(f[j][0], f[(j + s) & 3][1], 0x0c0c0500u, f[(j + 2 * s) & 3][2], f[(j + 3 * s) & 3][3],
+                          0x07020c0cu, key(4 * NR + j));
         }
     } else {
         uint32_t g[4][4];  // InvS bytes, zero-extended
@@ -319,9 +320,8 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t m = g[j][0] | (g[(j + s) & 3][1] << 8) | (g[(j + 2 * s) & 3][2] << 16) |
-                               (g[(j + 3 * s) & 3][3] << 24);
-            o[j] = m ^ key(4 * NR + j);
+            o[j] = merge4(g[j][0], g[(j + s) & 3][1], 0x0c0c0400u, g[(j + 2 * s) & 3][2], g[(j + 3 * s) & 3][3],
+                          0x04000c0cu, key(4 * NR + j));
         }
     }
     return make_uint4(o[0], o[1], o[2], o[3]);
