@@ -450,8 +450,8 @@ class Server:
     """
 
     def __init__(self, key_table_dev=None, in_pool=None, out_arena=None, *, n_slots=None, in_blocks=None,
-                 out_blocks=None, budget_bytes=32 << 30, chunk_blocks=1024, max_batch_items=1 << 18, nslots=4,
-                 bpt=1, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0):
+                 out_blocks=None, budget_bytes=32 << 30, chunk_blocks=2048, max_batch_items=1 << 18, nslots=4,
+                 bpt=4, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0):
         lib = _lib()
         _serve_sigs(lib)
         self._lib = lib
