@@ -487,6 +487,66 @@ def batched(torch, aes, inputs, bulk_rates):
 
 
 SATURATION_RHO = 1.5
+VERIFY_REQUESTS = 2000
+
+
+def verify_served(torch, aes, inputs, pool, kt, in_pool, out_arena):
+    """Served results against each request run alone: VERIFY_REQUESTS
+    requests of the serving mix, submitted in ten bursts 1 ms apart so that
+    batches form while others run, outputs kept (no auto release) until every
+    one has been compared, byte for byte, with the plain kernel's output for
+    that request alone.  Raises on any difference."""
+    import numpy as np
+    n = VERIFY_REQUESTS
+    pool_blocks = in_pool.numel() // 16
+    tr = inputs.request_trace(200, n, 1.0, len(pool))
+    g = inputs.rng(9, 200)
+    reqs = np.zeros(n, dtype=aes.REQUEST_DTYPE)
+    reqs["nblocks"] = np.minimum(tr.nblocks, pool_blocks)
+    reqs["in_block"] = (g.random(n) * (pool_blocks - reqs["nblocks"] + 1)).astype(np.uint64)
+    reqs["key_slot"] = tr.key_slot
+    reqs["decrypt"] = tr.decrypt
+    if int(reqs["nblocks"].sum()) * 16 > out_arena.numel():
+        raise RuntimeError("verification requests do not fit the output arena")
+    srv = aes.Server(kt, in_pool, out_arena, budget_bytes=2 * out_arena.numel(), chunk_blocks=2048,
+                     max_batch_items=1 << 18, nslots=4, bpt=4, auto_release=False)
+    for part in np.array_split(np.arange(n), 10):
+        srv.submit(reqs[part])
+        time.sleep(0.001)
+    got, t0 = [], time.time()
+    while sum(len(x) for x in got) < n:
+        got.append(srv.poll())
+        if time.time() - t0 > 60:
+            raise RuntimeError("served requests did not finish")
+        time.sleep(0.0002)
+    out = np.concatenate(got)
+    out = out[np.argsort(out["id"])]
+    if (out["status"] != aes.AES_SERVED_DONE).any():
+        raise RuntimeError("a verification request was not served")
+    scratch = torch.empty(int(reqs["nblocks"].max()) * 16, dtype=torch.uint8, device="cuda")
+    scheds = {}
+    bad = 0
+    for i in range(n):
+        q = reqs[i]
+        slot = int(q["key_slot"])
+        if slot not in scheds:
+            scheds[slot] = aes.aes_expand_key(pool[slot][1])
+        ks = scheds[slot]
+        lo, nb = int(q["in_block"]) * 16, int(q["nblocks"]) * 16
+        ob = int(out[i]["out_block"]) * 16
+        alone = scratch[:nb]
+        if q["decrypt"]:
+            aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, in_pool[lo:lo + nb], alone)
+        else:
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, in_pool[lo:lo + nb], alone)
+        if not torch.equal(alone, out_arena[ob:ob + nb]):
+            bad += 1
+    srv.release(out)
+    srv.close()
+    if bad:
+        raise RuntimeError("%d served requests differ from the request run alone" % bad)
+    return {"requests": n, "bytes": int(reqs["nblocks"].sum()) * 16,
+            "batches": int(len(np.unique(out["batch"]))), "mismatches": 0}
 
 
 def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=None):
@@ -544,13 +604,16 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
             rho, row["p50_ms"], row["p99_ms"], row["GB_s"], row["batches"]))
     st = srv.stats()
     srv.close()
+    verified = verify_served(torch, aes, inputs, pool, kt, in_pool, out_arena)
+    log("serving verified: %d requests, %d batches, all equal to the request run alone" % (
+        verified["requests"], verified["batches"]))
     del in_pool, out_arena
     torch.cuda.empty_cache()
     best = max(r["GB_s"] for r in rows)
     res = {"engine": "native (aes_server_*)", "peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget,
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
            "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"], "levels": rows,
-           "max_sustained_GB_s": best, "capacity": capacity}
+           "max_sustained_GB_s": best, "capacity": capacity, "verified": verified}
     if bulk_equivalent_gbps:
         res["max_sustained_vs_bulk"] = round(best / bulk_equivalent_gbps, 4)
         res["capacity_vs_bulk"] = round(capacity["GB_s"] / bulk_equivalent_gbps, 4)
