@@ -68,7 +68,7 @@ uint32_t inv_mix_column(uint32_t x)
     return r;
 }
 
-// Size buckets of the tuning table (blocks): <=4 KiB, <=64 KiB, <=1 MiB, <=8 MiB, larger.
+// Size buckets of the tuning table: <=4 KiB, <=64 KiB, <=1 MiB, <=8 MiB, <=32 MiB, larger.
 int size_bucket(uint64_t nblocks)
 {
     if (nblocks <= 256) return 0;
@@ -89,8 +89,8 @@ TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 // mid sizes timed with graph replays): small buffers are launch-bound and
 // prefer the smallest table fill; up to 32 MiB the 2-table placement (two
 // 1024-thread workgroups per CU, half the fill per workgroup) wins; above
-// that the 4-table placement with 64 bytes per thread is 4-8 % faster for
-// every key size and both directions.
+// that the 4-table placement with 64 bytes per thread is 4-8 % faster at
+// 256 MiB for every key size and both directions.
 struct TuneDefaults {
     static void set(TuneEntry& t, int bpt, int wg, int placement)
     {
