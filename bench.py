@@ -306,13 +306,15 @@ WARM_SECONDS = 0.05  # the engine clock takes a few tens of ms of load to ramp u
 
 
 def warm(torch, fn):
-    """Run fn back to back for WARM_SECONDS before a timing."""
+    """Run fn back to back, with no synchronisation in between, for about
+    WARM_SECONDS before a timing (the timed launches are back to back too)."""
     t0 = time.perf_counter()
-    while True:
+    fn()
+    torch.cuda.synchronize()
+    one = max(time.perf_counter() - t0, 1e-6)
+    for _ in range(max(1, min(4000, int(WARM_SECONDS / one)))):
         fn()
-        torch.cuda.synchronize()
-        if time.perf_counter() - t0 >= WARM_SECONDS:
-            return
+    torch.cuda.synchronize()
 
 
 def launch_ms(torch, fn, n):
