@@ -694,6 +694,9 @@ def main():
         "measured_roofs": None,
         "kernel_source_hash": kernel_source_hash(),
         "device": props.name,
+        "platform": {"arch": getattr(props, "gcnArchName", None), "cus": props.multi_processor_count,
+                     "hbm_bytes": props.total_memory, "hip": torch.version.hip, "torch": torch.__version__,
+                     "tune_file": os.environ.get(aes.TUNE_FILE_ENV)},
     }
     roofs = measured_roofs(torch, aes, inputs)
     result["measured_roofs"] = roofs

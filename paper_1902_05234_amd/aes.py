@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(HERE, "libaesgpu.so")
+TUNE_FILE_ENV = "AESGPU_TUNE_FILE"  # path of an autotune record to install when the library loads
 
 AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0, -1, -2, -3, -4, -5, -6
 AES_PLACEMENT_TTABLE4, AES_PLACEMENT_TTABLE2, AES_PLACEMENT_TTABLE1, AES_PLACEMENT_BITSLICED = 0, 1, 2, 3
@@ -108,6 +109,12 @@ def _lib() -> ctypes.CDLL:
                 f.argtypes = args
                 f.restype = res
             _lib_obj = lib
+            path = os.environ.get(TUNE_FILE_ENV)
+            if path:
+                # an autotune record (paper_1902_05234_amd.autotune --out) replaces the
+                # compiled-in defaults for every size it covers
+                from . import autotune
+                autotune.apply(autotune.load(path))
     return _lib_obj
 
 
