@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBRARY = os.path.join(HERE, "libaesgpu.so")
+# another build of the library (say, one with host sanitizers) can be named in AESGPU_LIBRARY
+LIBRARY = os.environ.get("AESGPU_LIBRARY") or os.path.join(HERE, "libaesgpu.so")
 TUNE_FILE_ENV = "AESGPU_TUNE_FILE"  # path of an autotune record to install when the library loads
 
 AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0, -1, -2, -3, -4, -5, -6

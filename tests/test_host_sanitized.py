@@ -1,0 +1,54 @@
+"""The library's host code is clean under AddressSanitizer and
+UndefinedBehaviorSanitizer: its host-side sources (argument checks, key
+schedule, batch planner, serving engine with its worker thread, host
+pipeline) are built on the CPU into a host-only library with the sanitizers
+on the host pass only and the kernel launchers stubbed
+(tests/sanitizer_stubs.cpp).  The CPU tests of the C ABI and of the serving
+engine's policy then run against that build in a child process with the
+sanitizer runtime preloaded; any report aborts the child."""
+import glob
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1902_05234_amd", "csrc")
+HOST_SOURCES = [os.path.join(CSRC, f) for f in ("aes_abi.cpp", "aes_serve.cpp", "aes_pipe.cpp")] + [
+    os.path.join(ROOT, "tests", "sanitizer_stubs.cpp")]
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _asan_runtime():
+    found = sorted(glob.glob("/opt/rocm*/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return found[-1] if found else None
+
+
+def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    from paper_1902_05234_amd import build
+    runtime = _asan_runtime()
+    if runtime is None:
+        pytest.skip("no clang AddressSanitizer runtime in the ROCm toolchain")
+    objs = []
+    for src in HOST_SOURCES:
+        obj = str(tmp_path / (os.path.splitext(os.path.basename(src))[0] + ".o"))
+        cmd = [build.hipcc(), "-std=c++17", "-fPIC", "-O1", "-g", "-x", "hip", "--cuda-host-only", *SANITIZE,
+               "-I" + build.INCLUDE, "-I" + CSRC, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-3000:]
+        objs.append(obj)
+    lib = str(tmp_path / "libaesgpu_host_sanitized.so")
+    r = subprocess.run([build.hipcc(), "-shared", "-fPIC", *objs, "-o", lib], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    logs = str(tmp_path / "report")  # the runtimes write here: the child's own stderr is captured by its pytest
+    env = dict(os.environ, AESGPU_LIBRARY=lib, LD_PRELOAD=runtime,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1:log_path=" + logs,
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1:log_path=" + logs)
+    tests = [os.path.join(ROOT, "tests", f) for f in ("test_host_abi.py", "test_native_serve.py")]
+    out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu", "-p", "no:cacheprovider",
+                          *tests], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    report = "".join(open(f).read() for f in sorted(glob.glob(logs + "*")))
+    assert out.returncode == 0 and not report, report[:4000] or (out.stdout[-3000:], out.stderr[-3000:])
+    assert " passed" in out.stdout
