@@ -5,7 +5,9 @@ pipeline) are built on the CPU into a host-only library with the sanitizers
 on the host pass only and the kernel launchers stubbed
 (tests/sanitizer_stubs.cpp).  The CPU tests of the C ABI and of the serving
 engine's policy then run against that build in a child process with the
-sanitizer runtime preloaded; any report aborts the child."""
+sanitizer runtime preloaded; any report aborts the child.  A second build
+with ThreadSanitizer runs the serving engine's CPU tests (a worker thread
+beside the submitting, polling and releasing thread) the same way."""
 import glob
 import os
 import subprocess
@@ -21,34 +23,54 @@ SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
 
-def _asan_runtime():
-    found = sorted(glob.glob("/opt/rocm*/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+def _runtime(name):
+    found = sorted(glob.glob("/opt/rocm*/lib/llvm/lib/clang/*/lib/linux/libclang_rt.%s-x86_64.so" % name))
     return found[-1] if found else None
 
 
-def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+def _build_host_library(tmp_path, flags, name):
     from paper_1902_05234_amd import build
-    runtime = _asan_runtime()
-    if runtime is None:
-        pytest.skip("no clang AddressSanitizer runtime in the ROCm toolchain")
     objs = []
     for src in HOST_SOURCES:
         obj = str(tmp_path / (os.path.splitext(os.path.basename(src))[0] + ".o"))
-        cmd = [build.hipcc(), "-std=c++17", "-fPIC", "-O1", "-g", "-x", "hip", "--cuda-host-only", *SANITIZE,
+        cmd = [build.hipcc(), "-std=c++17", "-fPIC", "-O1", "-g", "-x", "hip", "--cuda-host-only", *flags,
                "-I" + build.INCLUDE, "-I" + CSRC, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-3000:]
         objs.append(obj)
-    lib = str(tmp_path / "libaesgpu_host_sanitized.so")
+    lib = str(tmp_path / name)
     r = subprocess.run([build.hipcc(), "-shared", "-fPIC", *objs, "-o", lib], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
+    return lib
+
+
+def _run_tests(tmp_path, lib, runtime, options, test_files):
     logs = str(tmp_path / "report")  # the runtimes write here: the child's own stderr is captured by its pytest
-    env = dict(os.environ, AESGPU_LIBRARY=lib, LD_PRELOAD=runtime,
-               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1:log_path=" + logs,
-               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1:log_path=" + logs)
-    tests = [os.path.join(ROOT, "tests", f) for f in ("test_host_abi.py", "test_native_serve.py")]
+    env = dict(os.environ, AESGPU_LIBRARY=lib, LD_PRELOAD=runtime)
+    for var, opts in options.items():
+        env[var] = opts + ":log_path=" + logs
+    tests = [os.path.join(ROOT, "tests", f) for f in test_files]
     out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu", "-p", "no:cacheprovider",
                           *tests], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     report = "".join(open(f).read() for f in sorted(glob.glob(logs + "*")))
     assert out.returncode == 0 and not report, report[:4000] or (out.stdout[-3000:], out.stderr[-3000:])
     assert " passed" in out.stdout
+
+
+def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    runtime = _runtime("asan")
+    if runtime is None:
+        pytest.skip("no clang AddressSanitizer runtime in the ROCm toolchain")
+    lib = _build_host_library(tmp_path, SANITIZE, "libaesgpu_host_asan.so")
+    _run_tests(tmp_path, lib, runtime,
+               {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"},
+               ("test_host_abi.py", "test_native_serve.py"))
+
+
+def test_serving_engine_under_thread_sanitizer(tmp_path):
+    runtime = _runtime("tsan")
+    if runtime is None:
+        pytest.skip("no clang ThreadSanitizer runtime in the ROCm toolchain")
+    lib = _build_host_library(tmp_path, ["-Xarch_host", "-fsanitize=thread"], "libaesgpu_host_tsan.so")
+    _run_tests(tmp_path, lib, runtime, {"TSAN_OPTIONS": "halt_on_error=1"}, ("test_native_serve.py",))
