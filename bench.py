@@ -270,7 +270,7 @@ def cpu_baseline(b, args):
     t0 = time.perf_counter()
     o.ecb_encrypt(b["key"], probe, nthreads=cores)
     dt = max(time.perf_counter() - t0, 1e-6)
-    nbytes = int(min(256 * MiB, max(MiB, args.cpu_seconds / 2 / dt * MiB)))
+    nbytes = int(min(GiB, max(MiB, args.cpu_seconds / 2 / dt * MiB)))
     nbytes -= nbytes % MiB
     xs = b["x"][:nbytes].cpu().numpy()
     t0 = time.perf_counter()
