@@ -320,6 +320,7 @@ def ecb_encrypt(ks: KeySchedule, x, out=None, stream=None):
 
 
 def ecb_decrypt(ks: KeySchedule, x, out=None, stream=None):
+    """Decrypt a uint8 CUDA tensor of whole blocks; returns ``out``."""
     import torch
     out = torch.empty_like(x) if out is None else out
     return aes_ecb_decrypt(ks.rk_dec, ks.nr, x, out, stream=stream)
@@ -330,6 +331,14 @@ def ctr_crypt(ks: KeySchedule, iv: bytes, x, out=None, block_offset: int = 0, st
     import torch
     out = torch.empty_like(x) if out is None else out
     return aes_ctr_crypt(ks.rk_enc, ks.nr, iv, block_offset, x, out, stream=stream)
+
+
+def cbc_decrypt(ks: KeySchedule, iv: bytes, x, out=None, stream=None):
+    """CBC decryption of a uint8 CUDA tensor of whole blocks into a separate
+    ``out`` (in place is refused: block b reads ciphertext block b - 1)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    return aes_cbc_decrypt(ks.rk_dec, ks.nr, iv, x, out, stream=stream)
 
 
 # ---------------------------------------------------------------- batched ECB

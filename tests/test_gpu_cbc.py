@@ -46,6 +46,15 @@ def test_cbc_decrypt_random_ciphertext_matches_oracle(oracle_lib):
     assert_same(to_host(gpu_cbc_dec(ks, iv, to_dev(c))), oracle_lib.cbc_decrypt(key, iv, c), "random ciphertext")
 
 
+def test_cbc_decrypt_helper_allocates_output(oracle_lib):
+    key = inputs.random_key(713, 192)
+    iv = inputs.random_bytes(714, 16).tobytes()
+    x = inputs.random_bytes(715, 16 * 3001)
+    c = oracle_lib.cbc_encrypt(key, iv, x)
+    ks = aes.aes_expand_key(key)
+    assert_same(to_host(aes.cbc_decrypt(ks, iv, to_dev(c))), x, "cbc_decrypt helper")
+
+
 def test_cbc_decrypt_in_pieces_and_rejects_in_place(oracle_lib):
     torch = cuda()
     key = inputs.random_key(720, 128)
