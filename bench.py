@@ -229,6 +229,57 @@ def openssl_context(cores):
     return out
 
 
+def clock_under_load(torch, aes, b, seconds=2.0):
+    """Engine clock and socket power while the bulk encryption runs back to
+    back for `seconds` (after the timed steps): `rocm-smi --showclocks` and
+    `amd-smi metric -p`, sampled every 0.25 s from a thread.  None if the
+    tools are missing.  Context for the roofline: the published LDS peak
+    assumes 2.4 GHz."""
+    import shutil
+    import subprocess
+    import threading
+    if not shutil.which("rocm-smi"):
+        return None
+    samples, stop = [], threading.Event()
+
+    def sample():
+        while not stop.is_set():
+            clk = pw = None
+            try:
+                r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=5)
+                card = json.loads(r.stdout)
+                card = card[sorted(card)[0]]
+                clk = int(card["sclk clock speed:"].strip("()Mhz"))
+            except Exception:
+                pass
+            try:
+                r = subprocess.run(["amd-smi", "metric", "-p"], capture_output=True, text=True, timeout=5)
+                pw = float(r.stdout.split("SOCKET_POWER:")[1].split()[0])
+            except Exception:
+                pass
+            samples.append((clk, pw))
+            stop.wait(0.25)
+
+    ks = aes.aes_expand_key(b["key"])
+    th = threading.Thread(target=sample)
+    th.start()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, b["x"], b["c"])
+        torch.cuda.synchronize()
+    stop.set()
+    th.join()
+    clks = [c for c, _ in samples[1:] if c]
+    pws = [p for _, p in samples[1:] if p]
+    if not clks:
+        return None
+    mhz = sum(clks) / len(clks)
+    return {"sclk_MHz": round(mhz), "socket_power_W": round(sum(pws) / len(pws)) if pws else None,
+            "samples": len(clks), "lds_roof_at_clock_Glookup_s": round(LDS_PEAK / 1e9 * mhz * 1e6 / MI355X_CLOCK_HZ, 1),
+            "what": "bulk AES-128 encryption of 1 GiB back to back for %.0f s after the timed steps" % seconds}
+
+
 def measured_roofs(torch, aes, inputs):
     """The probes of the roofs: a 1 GiB device copy (HBM), conflict-free LDS
     lookups at 32 waves per CU, full-rate VALU chains; median of 5 timed
@@ -698,6 +749,12 @@ def main():
                      "hbm_bytes": props.total_memory, "hip": torch.version.hip, "torch": torch.__version__,
                      "tune_file": os.environ.get(aes.TUNE_FILE_ENV)},
     }
+    clock = clock_under_load(torch, aes, b)
+    if clock:
+        rl0 = result["roofline"]
+        clock["frac_at_clock"] = round(rl0["achieved"] / clock["lds_roof_at_clock_Glookup_s"], 4)
+        result["roofline"]["clock_under_load"] = clock
+        log("clock under load:", clock)
     roofs = measured_roofs(torch, aes, inputs)
     result["measured_roofs"] = roofs
     rl = result["roofline"]
