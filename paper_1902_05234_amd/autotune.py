@@ -4,9 +4,13 @@ Search space (plain path): blocks per thread {1, 2, 4} (16/32/64 bytes per
 thread) x workgroup size {64, 128, 256, 512, 1024} x table placement (the
 placements built into the library).  Every variant must reproduce the
 reference variant's output bit for bit (and decrypt back to the input)
-before it is timed.  The winner of each (key size, direction, size bucket)
-is written to a JSON record keyed by device and library source hash and can
-be installed into the library's tuning table with ``apply``.
+before it is timed.  Each (key size, direction, size bucket) is timed at two or
+three sizes spread over the bucket: the best variant for a bucket changes
+inside it (a buffer of a few wave units leaves waves idle with 64 bytes per
+thread but not with 16), so the winner is the variant whose worst ratio to
+the fastest variant over those sizes is highest.  The record is JSON keyed
+by device and library source hash and can be installed into the library's
+tuning table with ``apply``.
 
 Batched path: chunk size (blocks per work item) x blocks per thread.
 
@@ -29,8 +33,10 @@ WGS = (64, 128, 256, 512, 1024)
 PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1,
               aes.AES_PLACEMENT_BITSLICED)
 BITSLICE_MAX_WG = 256
-# representative sizes of the tuning buckets (bytes)
-BUCKET_SIZES = (4 << 10, 64 << 10, 1 << 20, 8 << 20, 32 << 20, 256 << 20)
+# sizes timed for each tuning bucket (bytes; bucket limits in aesgpu.h: 4 KiB,
+# 64 KiB, 2 MiB, 8 MiB, 32 MiB, larger)
+BUCKET_SIZES = ((2 << 10, 4 << 10), (16 << 10, 64 << 10), (256 << 10, 1 << 20, 2 << 20), (3 << 20, 8 << 20),
+                (12 << 20, 32 << 20), (256 << 20,))
 
 
 def source_hash() -> str:
@@ -166,15 +172,39 @@ def tune_batch(torch, n_messages: int = 20000, chunks=(256, 1024, 4096), reps: i
     return rows
 
 
-def run(sizes=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, rounds=3, log=print):
+def bucket_winner(per_size: dict) -> dict:
+    """The variant whose worst ratio to the fastest variant, over the sizes
+    timed for one bucket, is highest.  per_size: {nbytes: rows}."""
+    def vid(r):
+        return (r["bpt"], r["wg"], r["placement"])
+    best = {n: max(r["GB_s"] for r in rows) for n, rows in per_size.items()}
+    score = {}
+    for n, rows in per_size.items():
+        for r in rows:
+            score[vid(r)] = min(score.get(vid(r), 1.0), r["GB_s"] / best[n])
+    common = [v for v in score if all(any(vid(r) == v for r in rows) for rows in per_size.values())]
+    v = max(common, key=lambda k: score[k])
+    return {"bpt": v[0], "wg": v[1], "placement": v[2], "worst_ratio": round(score[v], 4)}
+
+
+def run(buckets=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, rounds=3, log=print):
+    """buckets: one tuple of sizes per tuning bucket (the library's bucket of
+    each tuple's sizes must agree)."""
     import torch
     rec = {"device": torch.cuda.get_device_properties(0).name, "source_hash": source_hash(),
            "created": time.strftime("%Y-%m-%dT%H:%M:%S"), "plain": {}, "batch": None}
     for kb in key_sizes:
         for dec in (False, True):
-            for n in sizes:
-                rows = tune_plain(torch, kb, dec, n, reps=reps, rounds=rounds, log=log)
-                rec["plain"]["%d/%s/%d" % (kb, "dec" if dec else "enc", n)] = {"winner": rows[0], "all": rows}
+            for sizes in buckets:
+                bucket = {aes.aes_size_bucket(n // 16) for n in sizes}
+                if len(bucket) != 1:
+                    raise ValueError("sizes %s span several tuning buckets" % (sizes,))
+                per_size = {n: tune_plain(torch, kb, dec, n, reps=reps, rounds=rounds, log=log) for n in sizes}
+                w = bucket_winner(per_size)
+                log("  %d-bit %s bucket %d: bpt=%d wg=%d placement=%d (worst ratio %.3f)" % (
+                    kb, "dec" if dec else "enc", bucket.pop(), w["bpt"], w["wg"], w["placement"], w["worst_ratio"]))
+                rec["plain"]["%d/%s/%d" % (kb, "dec" if dec else "enc", max(sizes))] = {
+                    "winner": w, "sizes": list(sizes), "all": {str(n): rows for n, rows in per_size.items()}}
     if batch_too:
         rec["batch"] = tune_batch(torch, log=log)
     return rec
@@ -204,14 +234,16 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--reps", type=int, default=10, help="launches per variant per round")
     ap.add_argument("--rounds", type=int, default=3, help="interleaved passes over the variants")
-    ap.add_argument("--sizes", default=None, help="comma-separated byte sizes (default: one per size bucket)")
+    ap.add_argument("--sizes", default=None,
+                    help="comma-separated byte sizes, each tuned on its own (default: two or three per size bucket)")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     if a.quick:
-        rec = run(sizes=(256 << 20,), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds, log=log)
+        rec = run(buckets=((256 << 20,),), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds,
+                  log=log)
     else:
-        sizes = tuple(int(x) for x in a.sizes.split(",")) if a.sizes else BUCKET_SIZES
-        rec = run(sizes=sizes, batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds, log=log)
+        buckets = tuple((int(x),) for x in a.sizes.split(",")) if a.sizes else BUCKET_SIZES
+        rec = run(buckets=buckets, batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds, log=log)
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
     log("wrote", a.out)

@@ -68,12 +68,12 @@ uint32_t inv_mix_column(uint32_t x)
     return r;
 }
 
-// Size buckets of the tuning table: <=4 KiB, <=64 KiB, <=1 MiB, <=8 MiB, <=32 MiB, larger.
+// Size buckets of the tuning table: <=4 KiB, <=64 KiB, <=2 MiB, <=8 MiB, <=32 MiB, larger.
 int size_bucket(uint64_t nblocks)
 {
     if (nblocks <= 256) return 0;
     if (nblocks <= 4096) return 1;
-    if (nblocks <= 65536) return 2;
+    if (nblocks <= 131072) return 2;
     if (nblocks <= 524288) return 3;
     if (nblocks <= 2097152) return 4;
     return 5;
@@ -85,12 +85,14 @@ struct TuneEntry {
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
 // Compiled-in defaults from MI355X autotune sweeps (paper_1902_05234_amd.autotune,
-// variants timed in interleaved passes; record in tuning/mi355x_sweep.json,
-// mid sizes timed with graph replays): small buffers are launch-bound and
-// prefer the smallest table fill; up to 32 MiB the 2-table placement (two
-// 1024-thread workgroups per CU, half the fill per workgroup) wins; above
-// that the 4-table placement with 64 bytes per thread is 4-8 % faster at
-// 256 MiB for every key size and both directions.
+// variants timed in interleaved passes at two or three sizes per bucket;
+// record in tuning/mi355x_sweep.json): up to 2 MiB launches are bound by
+// latency and prefer the smallest table fill (one table, 512-thread
+// workgroups); up to 32 MiB the 2-table placement (two 1024-thread
+// workgroups per CU) with 16 bytes per thread wins, since 32 or 64 bytes
+// per thread leave waves without a unit at these sizes; above that the
+// 4-table placement with 64 bytes per thread is 4-8 % faster at 256 MiB
+// for every key size and both directions.
 struct TuneDefaults {
     static void set(TuneEntry& t, int bpt, int wg, int placement)
     {
@@ -104,8 +106,8 @@ struct TuneDefaults {
             for (int d = 0; d < 2; ++d) {
                 for (int b = 0; b < 3; ++b)
                     set(g_tune[n][d][b], 1, 512, AES_PLACEMENT_TTABLE1);
-                set(g_tune[n][d][3], 2, 1024, AES_PLACEMENT_TTABLE2);
-                set(g_tune[n][d][4], 2, 1024, AES_PLACEMENT_TTABLE2);
+                set(g_tune[n][d][3], 1, 1024, AES_PLACEMENT_TTABLE2);
+                set(g_tune[n][d][4], 1, 1024, AES_PLACEMENT_TTABLE2);
                 set(g_tune[n][d][5], 4, 1024, AES_PLACEMENT_TTABLE4);
             }
         }

@@ -1,0 +1,35 @@
+"""Host-side logic of the autotuner (CPU): the sizes timed for each tuning
+bucket lie in that bucket, and a bucket's winner is the variant with the best
+worst-case ratio to the fastest variant over the bucket's sizes."""
+from paper_1902_05234_amd import aes, autotune
+
+
+def test_bucket_sizes_lie_in_their_buckets():
+    assert len(autotune.BUCKET_SIZES) == aes.AES_SIZE_BUCKETS
+    for b, sizes in enumerate(autotune.BUCKET_SIZES):
+        assert sizes and all(n % 16 == 0 for n in sizes)
+        assert {aes.aes_size_bucket(n // 16) for n in sizes} == {b}
+
+
+def _row(bpt, wg, pl, gbs):
+    return {"bpt": bpt, "wg": wg, "placement": pl, "GB_s": gbs, "ms": 1.0 / gbs}
+
+
+def test_bucket_winner_maximises_the_worst_ratio():
+    # v1 wins the large size, v2 is close there but far ahead at the small one
+    per_size = {
+        2 << 20: [_row(2, 1024, 1, 100.0), _row(1, 1024, 1, 50.0), _row(1, 512, 2, 80.0)],
+        8 << 20: [_row(2, 1024, 1, 90.0), _row(1, 1024, 1, 100.0), _row(1, 512, 2, 60.0)],
+    }
+    w = autotune.bucket_winner(per_size)
+    assert (w["bpt"], w["wg"], w["placement"]) == (2, 1024, 1)
+    assert abs(w["worst_ratio"] - 0.9) < 1e-9
+
+
+def test_bucket_winner_ignores_variants_missing_at_some_size():
+    per_size = {
+        1 << 20: [_row(1, 512, 2, 100.0), _row(4, 1024, 0, 99.0)],
+        2 << 20: [_row(1, 512, 2, 100.0)],
+    }
+    w = autotune.bucket_winner(per_size)
+    assert (w["bpt"], w["wg"], w["placement"]) == (1, 512, 2)
