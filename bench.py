@@ -738,7 +738,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "AES-128 ECB encrypt then decrypt of one 1 GiB device buffer (67,108,864 blocks), "
                                "seeded uniform random bytes and key", "keybits": 128, "bytes": b["nbytes"],
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "seeds": {"base": inputs.BASE_SEED, "data": "device_random_bytes(1)", "key": "random_key(1, 128)"}},
         "enc_GB_s": round(b["nbytes"] / (sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3) / 1e9, 1),
         "dec_GB_s": round(b["nbytes"] / (sum(b["dec_ms"]) / len(b["dec_ms"]) * 1e-3) / 1e9, 1),
         "roofline": roofline(b, traffic, aes),
