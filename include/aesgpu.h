@@ -202,6 +202,10 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  *            other overlap is AES_EINVAL.
  *   flags:   AES_PIPE_HOST_PINNED if both host buffers are page-locked (then
  *            they are copied directly, no staging).
+ * A buffer of at most one chunk and 4 MiB runs as a single kernel launch on
+ * host memory when the device maps it (the caller's pinned buffers, or the
+ * pipe's pinned staging): each range must lie inside one page-locked
+ * allocation mapped at the same address; otherwise it takes the copy path.
  * Synchronous: returns when host_out holds the result.  Calls on one pipe
  * are serialised.  Errors: AES_EINVAL for bad arguments, AES_EHIP for a
  * failed copy or launch (all slots are drained before returning).

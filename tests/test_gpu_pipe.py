@@ -64,6 +64,39 @@ def test_pipe_pinned_direct_and_in_place(oracle_lib):
         p.close()
 
 
+def test_pipe_pinned_small_buffers_run_on_host_memory(oracle_lib):
+    """Buffers of at most one chunk in pinned memory take the single-launch
+    path on host memory: ECB both ways, CTR with a partial block, slices that
+    start inside a pinned allocation, and in place."""
+    torch = cuda()
+    key = inputs.random_key(815, 256)
+    ks = aes.aes_expand_key(key)
+    iv = bytes(range(16))
+    p = aes.HostPipe(chunk_bytes=256 << 10, nslots=2, staging=False)
+    try:
+        big = torch.zeros(1 << 20, dtype=torch.uint8).pin_memory()
+        for n, at in ((16, 0), (1216, 4096), (18608, 12345 * 16), (256 << 10, 512 << 10)):
+            x = inputs.random_bytes(816 + n, n)
+            src = big[at:at + n]
+            src.copy_(torch.from_numpy(x))
+            dst = torch.zeros(n, dtype=torch.uint8).pin_memory()
+            p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, src, out=dst)
+            assert_same(dst.numpy(), oracle_lib.ecb_encrypt(key, x), "pinned enc n=%d" % n)
+            p.run(aes.AES_PIPE_ECB_DECRYPT, ks, dst, out=dst)
+            assert_same(dst.numpy(), x, "pinned dec in place n=%d" % n)
+            m = n - 5 if n > 16 else 11
+            p.run(aes.AES_PIPE_CTR, ks, src[:m], out=dst[:m], iv=iv)
+            assert_same(dst[:m].numpy(), oracle_lib.ctr_crypt(key, iv, x[:m]), "pinned ctr n=%d" % m)
+        x = inputs.random_bytes(819, 1024)
+        src = big[8:8 + 1024]                                      # not 16-byte aligned: copy path
+        src.copy_(torch.from_numpy(x))
+        dst = torch.zeros(1024, dtype=torch.uint8).pin_memory()
+        p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, src, out=dst)
+        assert_same(dst.numpy(), oracle_lib.ecb_encrypt(key, x), "unaligned pinned enc")
+    finally:
+        p.close()
+
+
 def test_pipe_ctr_across_chunks(oracle_lib, pipe):
     key = inputs.random_key(820, 128)
     ks = aes.aes_expand_key(key)
