@@ -665,7 +665,8 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     best = max(r["GB_s"] for r in rows)
     res = {"engine": "native (aes_server_*)", "peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget,
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
-           "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"], "levels": rows,
+           "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"],
+           "batches": st["batches"], "direct_batches": st["direct_batches"], "levels": rows,
            "max_sustained_GB_s": best, "capacity": capacity, "verified": verified}
     if bulk_equivalent_gbps:
         res["max_sustained_vs_bulk"] = round(best / bulk_equivalent_gbps, 4)

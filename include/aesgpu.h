@@ -353,6 +353,8 @@ typedef struct {
     uint64_t max_device_bytes_in_use;
     uint64_t arena_blocks_in_use;
     uint64_t pending;
+    uint64_t direct_batches; /* batches whose kernel read the work list from the pinned staging
+                                (device-mapped staging, at most 4096 items: no copy) */
 } aes_serve_stats;
 
 typedef struct aes_server aes_server;

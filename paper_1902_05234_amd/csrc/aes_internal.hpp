@@ -84,6 +84,11 @@ hipError_t launch_batch(const BatchArgs& args, int bpt, int grid, int wg, hipStr
 void batch_grid(uint64_t n_enc, uint64_t n_dec, uint64_t enc_blocks, uint64_t total_blocks, int wg, int max_grid,
                 int requested_enc_groups, int* grid, int* enc_groups);
 
+// [p, p + n) lies inside one page-locked host allocation that the current
+// device maps at the same address, so kernels may read and write it
+// (aes_pipe.cpp).
+bool host_range_device_mapped(const void* p, uint64_t n);
+
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 

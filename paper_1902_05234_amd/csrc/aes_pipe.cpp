@@ -57,6 +57,32 @@ struct aes_pipe {
     std::mutex mu;  // one run at a time per pipe
 };
 
+namespace aesgpu {
+
+// [p, p + n) lies inside one page-locked host allocation that the device maps
+// at the same address, so a kernel may read and write it.  A failed query
+// leaves no error behind for the next launch's hipGetLastError.
+bool host_range_device_mapped(const void* p, uint64_t n)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeHost || a.devicePointer != p)
+        return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+    return q >= b && n <= size && q - b <= size - n;
+}
+
+}  // namespace aesgpu
+
 using namespace aesgpu;
 
 namespace {
@@ -79,28 +105,6 @@ bool overlap_partial(const void* a, const void* b, uint64_t n)
 }
 
 constexpr uint64_t kDirectMax = 4ull << 20;
-
-// [p, p + n) lies inside one page-locked host allocation that the device maps
-// at the same address, so a kernel may read and write it.  A failed query
-// leaves no error behind for the next launch's hipGetLastError.
-bool device_mapped(const void* p, uint64_t n)
-{
-    hipPointerAttribute_t a{};
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    if (a.type != hipMemoryTypeHost || a.devicePointer != p)
-        return false;
-    hipDeviceptr_t base = nullptr;
-    size_t size = 0;
-    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    const uintptr_t b = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
-    return q >= b && n <= size && q - b <= size - n;
-}
 
 // The kernel for the bytes [off, off + len) of the message, in -> out on stream.
 hipError_t launch_piece(int op, int nr, const RoundKeys& keys, const Counter128& c0, uint64_t off, const void* in,
@@ -170,7 +174,7 @@ static int pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
     }
     p->chunk = cfg->chunk_bytes;
     p->has_pinned = cfg->pinned != nullptr;
-    p->staging_mapped = p->has_pinned && device_mapped(cfg->pinned, need);
+    p->staging_mapped = p->has_pinned && host_range_device_mapped(cfg->pinned, need);
     try {
         p->slots.resize((size_t)cfg->nslots);
     } catch (...) {
@@ -256,7 +260,8 @@ static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8
         const void* kin = nullptr;
         void* kout = nullptr;
         const bool aligned = ((reinterpret_cast<uintptr_t>(host_in) | reinterpret_cast<uintptr_t>(host_out)) & 15u) == 0;
-        if (!staged && aligned && device_mapped(host_in, nbytes) && device_mapped(host_out, nbytes)) {
+        if (!staged && aligned && host_range_device_mapped(host_in, nbytes) &&
+            host_range_device_mapped(host_out, nbytes)) {
             kin = host_in;
             kout = host_out;
         } else if (staged && p->staging_mapped) {

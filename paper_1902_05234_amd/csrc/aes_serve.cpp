@@ -5,7 +5,10 @@
 // every admitted, unfinished request) and the output arena allow; whenever
 // one of the stream slots is free, everything admitted so far is planned into
 // work items (same planner as aes_batch_plan), copied to that slot's device
-// work list from pinned staging, and run as one persistent batch launch.
+// work list from pinned staging, and run as one persistent batch launch.  A
+// work list of at most kDirectItems items is not copied: when the staging is
+// host memory the device maps (checked once at creation), the kernel reads
+// the items from it, which saves a copy over the host link per light batch.
 // Slots are polled with events; a finished request releases its budget at
 // once and its output space when the caller releases it (or immediately with
 // auto_release).  All device memory (work lists, counters, arenas) comes
@@ -31,6 +34,8 @@
 namespace aesgpu {
 
 int device_cu_count();
+
+constexpr size_t kDirectItems = 4096;
 
 namespace {
 
@@ -114,6 +119,7 @@ struct aes_server {
     void* out_arena = nullptr;
     size_t out_blocks = 0;
     std::vector<aesgpu::Slot> slots;
+    bool staging_mapped = false;  // kernels may read the work items from the pinned staging
     aesgpu::Arena arena{0};
     aesgpu::Clock::time_point t0;
 
@@ -129,6 +135,7 @@ struct aes_server {
     std::deque<aesgpu::Req*> pending;
     uint64_t in_use = 0;
     int batches = 0;
+    std::atomic<uint64_t> direct_batches{0};
     std::atomic<uint64_t> max_in_use{0};
     std::atomic<int> last_error{AES_OK};
     std::atomic<bool> broken{false};       // the worker stopped on an internal failure
@@ -194,13 +201,18 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
         return true;
     }
     const size_t n = ne + nd;
-    hipError_t e = hipMemcpyAsync(sl.items_dev, sl.staging, n * sizeof(aes_work_item), hipMemcpyHostToDevice,
-                                  sl.stream);
+    const bool direct = s->staging_mapped && n <= kDirectItems;
+    if (direct)
+        s->direct_batches.fetch_add(1, std::memory_order_relaxed);
+    hipError_t e = direct ? hipSuccess
+                          : hipMemcpyAsync(sl.items_dev, sl.staging, n * sizeof(aes_work_item),
+                                           hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) {
         int grid = 0, enc_groups = 0;
         batch_grid(ne, nd, enc_b, tot_b, s->cfg.wg, s->cfg.grid > 0 ? s->cfg.grid : s->cus, -1, &grid,
                    &enc_groups);
-        BatchArgs a{reinterpret_cast<const WorkItem*>(sl.items_dev), (uint32_t)ne, (uint32_t)nd, s->key_table,
+        const void* items = direct ? static_cast<const void*>(sl.staging) : static_cast<const void*>(sl.items_dev);
+        BatchArgs a{static_cast<const WorkItem*>(items), (uint32_t)ne, (uint32_t)nd, s->key_table,
                     (uint32_t)s->n_slots, s->in_pool, s->out_arena, (uint64_t)s->in_blocks, (uint64_t)s->out_blocks,
                     sl.counters_dev, (uint32_t)enc_groups};
         e = launch_batch(a, s->cfg.bpt, grid, s->cfg.wg, sl.stream);
@@ -422,6 +434,8 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
         delete s;
         return rc;
     }
+    if (!c.dry_run)
+        s->staging_mapped = host_range_device_mapped(staging_host, aes_server_staging_bytes(cfg));
     s->t0 = Clock::now();
     try {
         s->worker = std::thread(worker_main, s);
@@ -531,6 +545,7 @@ static int server_stats_impl(aes_server* s, aes_serve_stats* st)
     st->max_device_bytes_in_use = s->max_in_use.load(std::memory_order_relaxed);
     st->arena_blocks_in_use = s->arena_used_pub.load(std::memory_order_relaxed);
     st->pending = s->pending_pub.load(std::memory_order_relaxed) + s->incoming.size();
+    st->direct_batches = s->direct_batches.load(std::memory_order_relaxed);
     return AES_OK;
 }
 

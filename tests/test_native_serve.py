@@ -140,6 +140,52 @@ def test_native_served_results_equal_the_request_alone(oracle_lib):
 
 
 @pytest.mark.gpu
+def test_native_light_batches_read_items_from_pinned_staging(oracle_lib):
+    """Batches of at most 4096 work items are launched on the work list in
+    the pinned staging (no copy to the device): thirty bursts of ten small
+    requests reuse the four slots many times, and every result must equal
+    the request run alone."""
+    import torch
+    from paper_1902_05234_amd import batch
+    pool = inputs.key_pool(8, 16)
+    kt = batch.key_table([k for _, k in pool])
+    in_pool = inputs.device_random_bytes(8, 32 << 20)
+    out_arena = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    srv = aes.Server(kt, in_pool, out_arena, budget_bytes=256 << 20, chunk_blocks=512, nslots=4,
+                     auto_release=False)
+    r = requests(300, 9, max_blocks=6000, pool_blocks=in_pool.numel() // 16, slots=len(pool))
+    for part in range(30):
+        srv.submit(r[10 * part:10 * part + 10])
+        time.sleep(0.0003)
+    out = wait_all(srv, 300)
+    assert (out["status"] == aes.AES_SERVED_DONE).all()
+    st = srv.stats()
+    assert st["batches"] >= 8
+    assert st["direct_batches"] == st["batches"], "every batch here fits the direct work-list path"
+    scheds = [aes.aes_expand_key(k) for _, k in pool]
+    for i, q in enumerate(r):
+        ks = scheds[int(q["key_slot"])]
+        lo, n = int(q["in_block"]) * 16, int(q["nblocks"]) * 16
+        ob = int(out[i]["out_block"]) * 16
+        x = in_pool[lo:lo + n]
+        alone = torch.empty_like(x)
+        if q["decrypt"]:
+            aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, x, alone)
+        else:
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, alone)
+        assert torch.equal(alone, out_arena[ob:ob + n]), "request %d differs from the request alone" % i
+    q = r[7]
+    lo, n = int(q["in_block"]) * 16, int(q["nblocks"]) * 16
+    ob = int(out[7]["out_block"]) * 16
+    key = pool[int(q["key_slot"])][1]
+    x = in_pool[lo:lo + n].cpu().numpy()
+    want = oracle_lib.ecb_decrypt(key, x) if q["decrypt"] else oracle_lib.ecb_encrypt(key, x)
+    assert np.array_equal(out_arena[ob:ob + n].cpu().numpy(), want)
+    srv.release(out)
+    srv.close()
+
+
+@pytest.mark.gpu
 def test_native_replay_reports_latency():
     import torch
     from paper_1902_05234_amd import batch
