@@ -10,7 +10,8 @@ before timing starts.  Prints ONE JSON line:
                (encrypt + decrypt bytes / wall time of the timed steps)
   roofline     the encrypt kernel against the LDS lookup roof (the binding
                unit: 16 table lookups per block per round), with the HBM and
-               VALU roofs beside it
+               VALU roofs beside it, the HBM bytes rocprofv3 counted, and the
+               engine clock and socket power held under load
   cpu_baseline the CPU oracle (byte-wise FIPS-197, all host cores) on a
                bounded slice of the same workload
   batched      20,000 mixed messages in one persistent launch (graph replay)
@@ -19,16 +20,19 @@ before timing starts.  Prints ONE JSON line:
                time: graph replays up to 64 MiB, event-timed launches above), plus
                an all-zero control, CTR and CBC decryption at 1 GiB
   host_path    the paper's file sizes (1,202 ... 1,190,402 bytes) host buffer
-               in, host buffer out (copies included), pinned and pageable,
-               beside the paper's own GPU times; and the 1 GiB pinned rate
+               in, host buffer out (host-link transfers included), pinned and
+               pageable, beside the paper's own GPU times; and the 1 GiB
+               pinned rate
   serving      open-loop Poisson requests (80 % 64 B-16 KiB, 20 % 1-64 MiB,
-               4,096 resident keys, 32 GiB device budget) at offered loads
-               rho x the batched rate: p50/p99 latency and sustained GB/s
+               4,096 resident keys, 32 GiB device budget, 20,000 requests per
+               level) at offered loads rho x the batched rate: p50/p99 latency
+               and sustained GB/s; the engine's capacity under overload; 2000
+               served requests checked against each request run alone
 
-Flags: --gpus N (only 1 is supported), --steps K, --warmup W,
---no-batch / --no-sweep / --no-cpu / --no-host / --no-serve to skip sections,
---profile to run only a
-few bulk and copy launches (for rocprofv3).
+Flags: --gpus N (only 1 is supported), --steps K (default 100), --warmup W
+(default 30), --no-batch / --no-sweep / --no-cpu / --no-host / --no-serve to
+skip sections, --profile to run only a few bulk and copy launches (for
+rocprofv3).
 """
 from __future__ import annotations
 
