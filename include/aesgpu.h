@@ -263,13 +263,21 @@ typedef struct {
     uint32_t key_slot;
 } aes_work_item;
 
+/* Largest work item, in blocks (256 MiB).  One wave walks an item alone, so
+ * items are meant to be small: the batched launch and the serving engine are
+ * tuned at 2048-4096 blocks. */
+#define AES_MAX_ITEM_BLOCKS (1u << 24)
+
 /*
  * aes_batch_plan -- host only.  Splits msgs[0..nmsgs) into work items of at
  * most chunk_blocks blocks, all encryption items first, then all decryption
  * items, in message order.  items: host array of cap entries.  *n_enc and
  * *n_dec receive the item counts even when the capacity is too small
  * (AES_ERANGE), so a caller can size the array.  Messages with nblocks == 0
- * produce no items.
+ * produce no items.  Errors: chunk_blocks outside [1, AES_MAX_ITEM_BLOCKS] or a
+ * message whose in_block + nblocks or out_block + nblocks passes 2^64:
+ * AES_EINVAL with both counts 0; more than 2^32 - 1 items in all: AES_ERANGE
+ * with both counts 0.  Nothing is written to items unless the call succeeds.
  */
 int aes_batch_plan(const aes_msg *msgs, size_t nmsgs, uint32_t chunk_blocks, aes_work_item *items, size_t cap,
                    size_t *n_enc, size_t *n_dec);
@@ -292,7 +300,8 @@ typedef struct {
  *                  workgroup resets [0..2] to zero, so the launch can be
  *                  replayed, e.g. from a captured HIP graph), [3] the number of
  *                  items rejected by the in-kernel checks (slot out of range,
- *                  blocks outside an arena); [3] is never reset by the kernel.
+ *                  blocks outside an arena, more than AES_MAX_ITEM_BLOCKS
+ *                  blocks); [3] is never reset by the kernel.
  *   cfg:           may be NULL for defaults.
  * Launches that share counters_dev must not overlap in time.
  */
@@ -324,7 +333,8 @@ typedef struct {
 } aes_request;
 
 #define AES_SERVED_DONE 0
-#define AES_SERVED_REJECTED 1 /* can never run: empty, over budget/arena, bad slot, outside the pool */
+#define AES_SERVED_REJECTED 1 /* can never run: empty, over budget/arena, more work items than
+                                 max_batch_items, bad slot, outside the pool */
 #define AES_SERVED_FAILED 2   /* its batch failed to launch or run */
 typedef struct {
     uint64_t id;          /* submission order, from 0 */
@@ -339,7 +349,7 @@ typedef struct {
 
 typedef struct {
     uint64_t budget_bytes;     /* cap on input + output bytes of admitted, unfinished requests */
-    uint32_t chunk_blocks;     /* work-item size */
+    uint32_t chunk_blocks;     /* work-item size, 1..AES_MAX_ITEM_BLOCKS */
     uint32_t max_batch_items;  /* work items per batch (sizes the workspace) */
     int32_t nslots;            /* batches in flight, 1..16 (one stream each) */
     int32_t bpt, wg, grid;     /* batch kernel shape (grid 0 = one workgroup per CU) */

@@ -26,6 +26,7 @@ AES_SIZE_BUCKETS = 6
 
 MSG_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u8"),
                       ("key_slot", "<u4"), ("decrypt", "<u4")])
+AES_MAX_ITEM_BLOCKS = 1 << 24  # largest work item (blocks), as in the C header
 ITEM_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u4"), ("key_slot", "<u4")])
 assert MSG_DTYPE.itemsize == 32 and ITEM_DTYPE.itemsize == 24
 
@@ -349,9 +350,9 @@ def aes_batch_plan(msgs: np.ndarray, chunk_blocks: int):
     ne, nd = ctypes.c_size_t(0), ctypes.c_size_t(0)
     rc = lib.aes_batch_plan(msgs.ctypes.data if msgs.size else None, msgs.size, int(chunk_blocks), None, 0,
                             ctypes.byref(ne), ctypes.byref(nd))
-    if rc not in (AES_OK, AES_ERANGE):
-        _check(rc)
     n = ne.value + nd.value
+    if rc != AES_OK and not (rc == AES_ERANGE and n > 0):  # ERANGE with counts: only the capacity was short
+        _check(rc)
     items = np.zeros(n, dtype=ITEM_DTYPE)
     if n:
         _check(lib.aes_batch_plan(msgs.ctypes.data, msgs.size, int(chunk_blocks), items.ctypes.data, n,

@@ -455,24 +455,30 @@ int aes_batch_plan(const aes_msg* msgs, size_t nmsgs, uint32_t chunk_blocks, aes
     *n_enc = *n_dec = 0;
     if (nmsgs > 0 && msgs == nullptr)
         return fail(AES_EINVAL, "null message array with nmsgs=%zu", nmsgs);
-    if (chunk_blocks == 0)
-        return fail(AES_EINVAL, "chunk_blocks must be positive");
-    size_t ne = 0, nd = 0;
-    for (size_t i = 0; i < nmsgs; ++i) {
-        const uint64_t n = msgs[i].nblocks;
-        const uint64_t c = (n + chunk_blocks - 1) / chunk_blocks;
-        (msgs[i].decrypt ? nd : ne) += c;
-    }
-    *n_enc = ne;
-    *n_dec = nd;
-    if (ne + nd > UINT32_MAX)
-        return fail(AES_ERANGE, "too many work items (%zu)", ne + nd);
-    if (ne + nd > cap || (ne + nd > 0 && items == nullptr))
-        return fail(AES_ERANGE, "work list needs %zu items, capacity is %zu", ne + nd, cap);
-    size_t ie = 0, id = ne;
+    if (chunk_blocks == 0 || chunk_blocks > AES_MAX_ITEM_BLOCKS)
+        return fail(AES_EINVAL, "chunk_blocks must be in [1, %u], got %u", AES_MAX_ITEM_BLOCKS, chunk_blocks);
+    // Count first (the counts are returned even when cap is too small); every
+    // sum is checked, so the fill below writes exactly the counted items.
+    uint64_t ne = 0, nd = 0;
     for (size_t i = 0; i < nmsgs; ++i) {
         const aes_msg& m = msgs[i];
-        for (uint64_t off = 0; off < m.nblocks; off += chunk_blocks) {
+        if (m.in_block > UINT64_MAX - m.nblocks || m.out_block > UINT64_MAX - m.nblocks)
+            return fail(AES_EINVAL, "message %zu: block range passes 2^64", i);
+        const uint64_t c = m.nblocks / chunk_blocks + (m.nblocks % chunk_blocks != 0);
+        if (c > UINT32_MAX - (ne + nd))
+            return fail(AES_ERANGE, "more than 2^32 - 1 work items");
+        (m.decrypt ? nd : ne) += c;
+    }
+    *n_enc = (size_t)ne;
+    *n_dec = (size_t)nd;
+    if (ne + nd > cap || (ne + nd > 0 && items == nullptr))
+        return fail(AES_ERANGE, "work list needs %llu items, capacity is %zu", (unsigned long long)(ne + nd), cap);
+    size_t ie = 0, id = (size_t)ne;
+    for (size_t i = 0; i < nmsgs; ++i) {
+        const aes_msg& m = msgs[i];
+        const uint64_t c = m.nblocks / chunk_blocks + (m.nblocks % chunk_blocks != 0);
+        for (uint64_t k = 0; k < c; ++k) {
+            const uint64_t off = k * chunk_blocks;  // < nblocks: no overflow
             aes_work_item& it = items[m.decrypt ? id++ : ie++];
             it.in_block = m.in_block + off;
             it.out_block = m.out_block + off;

@@ -13,8 +13,9 @@
 // other list.  The last workgroup to finish resets the claim counters, so a
 // captured graph can replay the launch with no separate reset node.
 //
-// Every item is checked against the arena sizes and the key-table size
-// before use; a bad item is skipped and counted in counters[3].
+// Every item is checked against the arena sizes, the key-table size and the
+// largest item size before use; a bad item is skipped and counted in
+// counters[3].
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cstdint>
@@ -38,26 +39,30 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
         k[i] = __builtin_amdgcn_readfirstlane(kp[i]);
     auto key = [&](int i) { return k[i]; };
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t b0 = 0; b0 < nblocks; b0 += 64u * BPT) {
-        const uint32_t first = b0 + lane;
-        if (b0 + 64u * BPT <= nblocks) {
-            uint4 x[BPT];
+    // Whole units first, then the ragged one: every index stays below
+    // nblocks + 64*BPT, so no 32-bit sum wraps.
+    const uint32_t span = 64u * BPT;
+    const uint32_t full = nblocks / span;
+    for (uint32_t u = 0; u < full; ++u) {
+        const uint32_t first = u * span + lane;
+        uint4 x[BPT];
 #pragma unroll
-            for (int j = 0; j < BPT; ++j)
-                x[j] = in[first + 64u * j];
+        for (int j = 0; j < BPT; ++j)
+            x[j] = in[first + 64u * j];
 #pragma unroll
-            for (int j = 0; j < BPT; ++j)
-                x[j] = crypt_block<NR, kDecrypt, kPlace4>(x[j], lds, lb, key);
+        for (int j = 0; j < BPT; ++j)
+            x[j] = crypt_block<NR, kDecrypt, kPlace4>(x[j], lds, lb, key);
 #pragma unroll
-            for (int j = 0; j < BPT; ++j)
-                out[first + 64u * j] = x[j];
-        } else {
+        for (int j = 0; j < BPT; ++j)
+            out[first + 64u * j] = x[j];
+    }
+    const uint32_t b0 = full * span;
+    if (b0 < nblocks) {
 #pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                uint32_t b = first + 64u * j;
-                if (b < nblocks)
-                    out[b] = crypt_block<NR, kDecrypt, kPlace4>(in[b], lds, lb, key);
-            }
+        for (int j = 0; j < BPT; ++j) {
+            const uint32_t b = b0 + lane + 64u * j;
+            if (b < nblocks)
+                out[b] = crypt_block<NR, kDecrypt, kPlace4>(in[b], lds, lb, key);
         }
     }
 }
@@ -85,8 +90,8 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
                                ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it.out_block >> 32)) << 32);
         const uint32_t nb = __builtin_amdgcn_readfirstlane(it.nblocks);
         const uint32_t slot = __builtin_amdgcn_readfirstlane(it.key_slot);
-        const bool ok = slot < n_slots && in_b <= in_blocks && nb <= in_blocks - in_b && out_b <= out_blocks &&
-                        nb <= out_blocks - out_b;
+        const bool ok = slot < n_slots && nb <= AES_MAX_ITEM_BLOCKS && in_b <= in_blocks && nb <= in_blocks - in_b &&
+                        out_b <= out_blocks && nb <= out_blocks - out_b;
         const uint32_t* kp = key_table + (uint64_t)(ok ? slot : 0u) * kSlotWords;
         const int nr = ok ? (int)__builtin_amdgcn_readfirstlane(kp[kSlotNr]) : 0;
         const uint32_t* kd = kp + (kDecrypt ? 64 : 0);

@@ -165,10 +165,16 @@ void finish(aes_server* s, Slot& sl, int status, double t)
     s->completed.insert(s->completed.end(), done.begin(), done.end());
 }
 
+// Work items of a request of n blocks.
+uint64_t items_of(uint64_t n, uint32_t chunk) { return n / chunk + (n % chunk != 0); }
+
 bool valid(const aes_server* s, const aes_request& r)
 {
-    return r.nblocks > 0 && 2 * 16 * r.nblocks <= s->cfg.budget_bytes && r.nblocks <= s->out_blocks &&
-           r.key_slot < s->n_slots && r.in_block <= s->in_blocks && r.nblocks <= s->in_blocks - r.in_block;
+    // the arena bounds come first and the budget is divided, so no product
+    // wraps; a request must fit one batch, else it would hold the FIFO forever
+    return r.nblocks > 0 && r.nblocks <= s->out_blocks && r.in_block <= s->in_blocks &&
+           r.nblocks <= s->in_blocks - r.in_block && r.nblocks <= s->cfg.budget_bytes / 32 &&
+           items_of(r.nblocks, s->cfg.chunk_blocks) <= s->cfg.max_batch_items && r.key_slot < s->n_slots;
 }
 
 bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
@@ -177,7 +183,7 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
     size_t ne = 0, nd = 0;
     uint64_t enc_b = 0, tot_b = 0;
     for (Req* q : batch) {
-        const uint64_t c = (q->r.nblocks + chunk - 1) / chunk;
+        const uint64_t c = items_of(q->r.nblocks, chunk);
         (q->r.decrypt ? nd : ne) += c;
         tot_b += q->r.nblocks;
         if (!q->r.decrypt)
@@ -185,7 +191,9 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
     }
     size_t ie = 0, id = ne;
     for (Req* q : batch) {
-        for (uint64_t off = 0; off < q->r.nblocks; off += chunk) {
+        const uint64_t c = items_of(q->r.nblocks, chunk);
+        for (uint64_t k = 0; k < c; ++k) {
+            const uint64_t off = k * chunk;
             aes_work_item& it = sl.staging[q->r.decrypt ? id++ : ie++];
             it.in_block = q->r.in_block + off;
             it.out_block = q->out_block + off;
@@ -307,9 +315,9 @@ void worker_loop(aes_server* s)
                     s->completed.push_back(q);
                     continue;
                 }
-                const uint64_t need = (q->r.nblocks + s->cfg.chunk_blocks - 1) / s->cfg.chunk_blocks;
-                const uint64_t bytes = 2 * 16 * q->r.nblocks;
-                if (items + need > s->cfg.max_batch_items || s->in_use + bytes > s->cfg.budget_bytes)
+                const uint64_t need = items_of(q->r.nblocks, s->cfg.chunk_blocks);
+                const uint64_t bytes = 2 * 16 * q->r.nblocks;  // valid(): at most the budget
+                if (items + need > s->cfg.max_batch_items || bytes > s->cfg.budget_bytes - s->in_use)
                     break;
                 uint64_t start;
                 if (!s->arena.alloc(q->r.nblocks, &start))
@@ -370,10 +378,11 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
         return fail(AES_EINVAL, "null config or output pointer");
     *out = nullptr;
     const aes_serve_config& c = *cfg;
-    if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.max_batch_items == 0 || c.budget_bytes == 0 ||
-        (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 || c.wg > 1024 || c.wg % 64)
-        return fail(AES_EINVAL, "serve config out of range (nslots 1..16, chunk/items/budget > 0, bpt 1/2/4, "
-                                "wg multiple of 64 in [64, 1024])");
+    if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.chunk_blocks > AES_MAX_ITEM_BLOCKS ||
+        c.max_batch_items == 0 || c.budget_bytes == 0 || (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 ||
+        c.wg > 1024 || c.wg % 64)
+        return fail(AES_EINVAL, "serve config out of range (nslots 1..16, chunk 1..AES_MAX_ITEM_BLOCKS, "
+                                "items/budget > 0, bpt 1/2/4, wg multiple of 64 in [64, 1024])");
     if (!c.dry_run && (key_table_dev == nullptr || in_pool == nullptr || out_arena == nullptr ||
                        workspace_dev == nullptr || staging_host == nullptr))
         return fail(AES_EINVAL, "null key table, input pool, output arena, workspace or staging");

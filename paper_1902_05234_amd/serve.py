@@ -108,6 +108,8 @@ class Scheduler:
             raise AdmissionError("request %d (%d bytes) exceeds the device budget" % (req.rid, req.nbytes))
         if req.nblocks <= 0:
             raise AdmissionError("request %d has no blocks" % req.rid)
+        if -(-req.nblocks // self.chunk) > self.max_items:
+            raise AdmissionError("request %d needs more work items than one batch holds" % req.rid)
         self.pending.append(req)
 
     def admit(self, now: float):
@@ -116,8 +118,8 @@ class Scheduler:
         batch, items = [], 0
         while self.pending:
             r = self.pending[0]
-            need_items = -(-r.nblocks // self.chunk)
-            if batch and items + need_items > self.max_items:
+            need_items = -(-r.nblocks // self.chunk)  # submit(): at most max_items
+            if items + need_items > self.max_items:
                 break
             if self.in_use + 2 * r.nbytes > self.budget:
                 break

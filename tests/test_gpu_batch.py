@@ -101,6 +101,31 @@ def test_bad_items_are_skipped_and_counted(oracle_lib):
     assert not out[16000:32000].any()
 
 
+def test_largest_item_runs_and_one_block_more_is_rejected(oracle_lib):
+    """An item of AES_MAX_ITEM_BLOCKS blocks (256 MiB, walked by one wave) is
+    encrypted; an item one block larger is skipped and counted."""
+    torch = cuda()
+    n = aes.AES_MAX_ITEM_BLOCKS
+    key = inputs.random_key(7, 128)
+    kt = batch.key_table([key])
+    in_arena = inputs.device_random_bytes(7, 16 * (n + 1))
+    out_arena = torch.zeros_like(in_arena)
+    items = np.zeros(2, dtype=aes.ITEM_DTYPE)
+    items[0] = (0, 0, n, 0)      # blocks [0, n): at the limit
+    items[1] = (0, 0, n + 1, 0)  # blocks [0, n]: over it
+    items_dev = torch.from_numpy(items.view(np.uint8).copy()).cuda()
+    counters = torch.zeros(4, dtype=torch.int32, device="cuda")
+    aes.aes_ecb_batch(items_dev, 2, 0, kt, in_arena, out_arena, counters)
+    torch.cuda.synchronize()
+    assert int(counters[3].item()) == 1
+    assert not out_arena[16 * n:].any(), "the rejected item wrote its last block"
+    win = 1 << 20
+    for off in (0, 16 * n - win):  # the first and the last MiB of the item
+        xw = in_arena[off:off + win].cpu().numpy()
+        j = first_mismatch(out_arena[off:off + win].cpu().numpy(), oracle_lib.ecb_encrypt(key, xw))
+        assert j is None, "window @%d: byte %d differs" % (off, j)
+
+
 def test_batch_config_2_full_mix(oracle_lib):
     """The full batched workload: 20,000 messages, log-uniform 16 B - 8 MiB,
     own key and key size each, half encrypt half decrypt (about 12.7 GB)."""

@@ -345,6 +345,44 @@ def test_batch_plan_capacity_and_errors():
     assert len(items) == 0 and ne_ == nd_ == 0
 
 
+def test_batch_plan_rejects_block_ranges_and_item_counts_that_wrap():
+    """Counting and filling agree for any message sizes: a range past 2^64 or
+    more than 2^32 - 1 items fails with zero counts and leaves items untouched."""
+    lib = aes._lib()
+    ne, nd = aes.ctypes.c_size_t(), aes.ctypes.c_size_t()
+    items = np.zeros(8, dtype=aes.ITEM_DTYPE)
+    items.view(np.uint8)[:] = 0xA5
+    before = items.copy()
+
+    def plan(m, chunk):
+        ne.value = nd.value = 123
+        rc = lib.aes_batch_plan(m.ctypes.data, len(m), chunk, items.ctypes.data, len(items),
+                                aes.ctypes.byref(ne), aes.ctypes.byref(nd))
+        return rc, ne.value, nd.value
+
+    m = make_msgs([20], [0])
+    assert plan(m, aes.AES_MAX_ITEM_BLOCKS + 1) == (aes.AES_EINVAL, 0, 0)
+    m["in_block"] = 2**64 - 10
+    assert plan(m, 8) == (aes.AES_EINVAL, 0, 0)
+    m = make_msgs([20], [1])
+    m["out_block"] = 2**64 - 19
+    assert plan(m, 8) == (aes.AES_EINVAL, 0, 0)
+    m = make_msgs([2**64 - 1], [0])
+    m["out_block"] = 0
+    assert plan(m, aes.AES_MAX_ITEM_BLOCKS) == (aes.AES_ERANGE, 0, 0)
+    m = make_msgs([2**39, 2**39], [0, 1])  # 2^31 items each: one more than fits
+    assert plan(m, 256) == (aes.AES_ERANGE, 0, 0)
+    assert (items == before).all()
+    with pytest.raises(aes.AesError):
+        aes.aes_batch_plan(make_msgs([2**64 - 1], [0]), 1)
+    # the largest item size splits exactly
+    n = 3 * aes.AES_MAX_ITEM_BLOCKS + 5
+    got, ne_, nd_ = aes.aes_batch_plan(make_msgs([n], [1]), aes.AES_MAX_ITEM_BLOCKS)
+    assert (ne_, nd_) == (0, 4)
+    assert got["nblocks"].tolist() == [aes.AES_MAX_ITEM_BLOCKS] * 3 + [5]
+    assert got["in_block"].tolist() == [k * aes.AES_MAX_ITEM_BLOCKS for k in range(4)]
+
+
 def test_tune_file_from_environment_replaces_defaults(tmp_path):
     """AESGPU_TUNE_FILE installs an autotune record when the library loads."""
     import json

@@ -68,6 +68,35 @@ def test_dry_run_rejects_what_can_never_run():
         assert out[i]["status"] == (aes.AES_SERVED_REJECTED if i in bad else aes.AES_SERVED_DONE), i
 
 
+def test_dry_run_rejects_a_size_whose_byte_count_wraps():
+    """2^59 blocks are 2^64 bytes in and out: rejected at once, not admitted as
+    zero bytes and left to block the queue."""
+    srv = aes.Server(n_slots=2, in_blocks=1 << 62, out_blocks=1 << 62, budget_bytes=1 << 30, chunk_blocks=256,
+                     max_batch_items=64, nslots=2, dry_run=True, dry_run_seconds=0.0002)
+    r = requests(3, 4, max_blocks=100, pool_blocks=100000, slots=2)
+    r[1]["in_block"] = 0
+    r[1]["nblocks"] = 1 << 59
+    srv.submit(r)
+    out = wait_all(srv, 3, timeout=10.0)
+    srv.close()
+    assert out["status"].tolist() == [aes.AES_SERVED_DONE, aes.AES_SERVED_REJECTED, aes.AES_SERVED_DONE]
+
+
+def test_dry_run_rejects_a_request_larger_than_one_batch():
+    """A request whose work items exceed max_batch_items could never be
+    admitted: it is rejected at once, and the requests behind it still run."""
+    srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=100000, budget_bytes=1 << 30, chunk_blocks=64,
+                     max_batch_items=4, nslots=2, dry_run=True, dry_run_seconds=0.0002)
+    r = requests(4, 5, max_blocks=100, pool_blocks=100000, slots=2)
+    r[1]["nblocks"] = 4 * 64 + 1
+    r[2]["nblocks"] = 4 * 64
+    srv.submit(r)
+    out = wait_all(srv, 4, timeout=10.0)
+    srv.close()
+    assert out["status"].tolist() == [aes.AES_SERVED_DONE, aes.AES_SERVED_REJECTED, aes.AES_SERVED_DONE,
+                                      aes.AES_SERVED_DONE]
+
+
 def test_dry_run_manual_release_gates_the_arena():
     srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=2000, budget_bytes=1 << 30, chunk_blocks=128,
                      max_batch_items=64, nslots=2, auto_release=False, dry_run=True, dry_run_seconds=0.0002)
@@ -89,8 +118,8 @@ def test_dry_run_manual_release_gates_the_arena():
 
 
 def test_create_rejects_bad_configs():
-    for kw in (dict(nslots=0), dict(nslots=17), dict(chunk_blocks=0), dict(bpt=3), dict(wg=100),
-               dict(budget_bytes=0), dict(max_batch_items=0)):
+    for kw in (dict(nslots=0), dict(nslots=17), dict(chunk_blocks=0), dict(chunk_blocks=aes.AES_MAX_ITEM_BLOCKS + 1),
+               dict(bpt=3), dict(wg=100), dict(budget_bytes=0), dict(max_batch_items=0)):
         args = dict(n_slots=1, in_blocks=10, out_blocks=10, dry_run=True)
         args.update(kw)
         with pytest.raises(aes.AesError):

@@ -128,6 +128,11 @@ def test_oversized_request_rejected_and_failures_release_budget():
     assert sch.in_use == 0 and sch.arena.used == 0
     with pytest.raises(AdmissionError):
         sch.submit(Request(999, 0, False, 0, 0, 0.0))
+    # a request must fit one batch's work list
+    small = Scheduler(1 << 30, arena_blocks=1 << 20, max_batch_items=4, chunk_blocks=64)
+    small.submit(Request(1000, 0, False, 0, 4 * 64, 0.0))
+    with pytest.raises(AdmissionError):
+        small.submit(Request(1001, 0, False, 0, 4 * 64 + 1, 0.0))
 
 
 # ------------------------------------------------------------------ GPU part
