@@ -380,7 +380,10 @@ int aes_server_create(const aes_serve_config *cfg, const uint32_t *key_table_dev
 int aes_server_submit(aes_server *s, const aes_request *reqs, size_t n, uint64_t *first_id);
 /* Moves up to cap finished requests (any order of ids) into out; *n = count. */
 int aes_server_poll(aes_server *s, aes_served *out, size_t cap, size_t *n);
-/* Frees the output space of finished requests (no-op with auto_release). */
+/* Frees the output space of finished requests (no-op with auto_release).
+ * Records with status AES_SERVED_DONE whose (out_block, nblocks) the engine
+ * does not hold as an unreleased output (released already, or never handed
+ * out) are skipped, and the call returns AES_EINVAL; the others are freed. */
 int aes_server_release(aes_server *s, const aes_served *done, size_t n);
 int aes_server_stats(aes_server *s, aes_serve_stats *stats);
 /* Finishes every submitted request, then frees the engine (not the buffers). */

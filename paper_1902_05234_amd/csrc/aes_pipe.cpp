@@ -155,6 +155,8 @@ static int pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
                     (unsigned long long)cfg->chunk_bytes);
     if (cfg->nslots < 1 || cfg->nslots > AES_PIPE_MAX_SLOTS)
         return fail(AES_EINVAL, "nslots must be in [1, %d], got %d", AES_PIPE_MAX_SLOTS, cfg->nslots);
+    if (cfg->chunk_bytes > UINT64_MAX / (uint64_t)cfg->nslots)
+        return fail(AES_EINVAL, "nslots * chunk_bytes passes 2^64");
     const uint64_t need = cfg->chunk_bytes * (uint64_t)cfg->nslots;
     if (cfg->dev == nullptr || cfg->dev_bytes < need)
         return fail(AES_EINVAL, "device workspace must hold nslots * chunk_bytes = %llu bytes",
@@ -286,8 +288,9 @@ static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8
     }
     const size_t ns = p->slots.size();
     int rc = AES_OK;
-    uint64_t chunk_index = 0;
-    for (uint64_t off = 0; off < nbytes && rc == AES_OK; off += p->chunk, ++chunk_index) {
+    const uint64_t nchunks = nbytes / p->chunk + (nbytes % p->chunk != 0);
+    for (uint64_t chunk_index = 0; chunk_index < nchunks && rc == AES_OK; ++chunk_index) {
+        const uint64_t off = chunk_index * p->chunk;  // < nbytes: no overflow
         Slot& s = p->slots[chunk_index % ns];
         rc = finish(s, dst, staged);
         if (rc != AES_OK)

@@ -128,13 +128,14 @@ struct aes_server {
     std::deque<aesgpu::Req*> incoming;
     std::vector<aesgpu::Req*> completed;
     std::vector<std::pair<uint64_t, uint64_t>> releases;  // (out_block, nblocks) released by the caller
+    std::map<uint64_t, uint64_t> outstanding;  // manual release: finished outputs not yet released (start -> blocks)
     uint64_t next_id = 0;
     bool stop = false;
 
     // worker-only state
     std::deque<aesgpu::Req*> pending;
     uint64_t in_use = 0;
-    int batches = 0;
+    std::atomic<uint64_t> batches{0};      // written by the worker, read by aes_server_stats
     std::atomic<uint64_t> direct_batches{0};
     std::atomic<uint64_t> max_in_use{0};
     std::atomic<int> last_error{AES_OK};
@@ -162,6 +163,9 @@ void finish(aes_server* s, Slot& sl, int status, double t)
     }
     sl.busy = false;
     std::lock_guard<std::mutex> g(s->mu);
+    if (!s->cfg.auto_release && status == AES_SERVED_DONE)
+        for (Req* q : done)
+            s->outstanding.emplace(q->out_block, q->r.nblocks);
     s->completed.insert(s->completed.end(), done.begin(), done.end());
 }
 
@@ -203,7 +207,7 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
     }
     sl.reqs = batch;
     sl.busy = true;
-    s->batches++;
+    s->batches.fetch_add(1, std::memory_order_relaxed);
     if (s->cfg.dry_run) {
         sl.dry_done = s->now() + s->cfg.dry_run_seconds;
         return true;
@@ -325,7 +329,7 @@ void worker_loop(aes_server* s)
                 s->pending.pop_front();
                 q->out_block = start;
                 q->admitted = s->now();
-                q->batch = s->batches;
+                q->batch = (int)s->batches.load(std::memory_order_relaxed);
                 s->in_use += bytes;
                 items += need;
                 batch.push_back(q);
@@ -534,15 +538,27 @@ static int server_release_impl(aes_server* s, const aes_served* done, size_t n)
         return AES_EINVAL;
     if (s->cfg.auto_release)
         return AES_OK;
+    int rc = AES_OK;
     {
+        // only ranges the engine handed out and that are still held go back to
+        // the arena: a repeated or made-up release would corrupt its free list
         std::lock_guard<std::mutex> g(s->mu);
-        for (size_t i = 0; i < n; ++i)
-            if (done[i].status == AES_SERVED_DONE)
-                s->releases.emplace_back(done[i].out_block, done[i].nblocks);
+        for (size_t i = 0; i < n; ++i) {
+            if (done[i].status != AES_SERVED_DONE)
+                continue;
+            auto it = s->outstanding.find(done[i].out_block);
+            if (it == s->outstanding.end() || it->second != done[i].nblocks) {
+                rc = fail(AES_EINVAL, "release of blocks [%llu, +%llu) that are not held",
+                          (unsigned long long)done[i].out_block, (unsigned long long)done[i].nblocks);
+                continue;
+            }
+            s->outstanding.erase(it);
+            s->releases.emplace_back(done[i].out_block, done[i].nblocks);
+        }
         s->submitted.fetch_add(1, std::memory_order_release);
     }
     s->cv.notify_one();
-    return AES_OK;
+    return rc;
 }
 
 static int server_stats_impl(aes_server* s, aes_serve_stats* st)
@@ -550,7 +566,7 @@ static int server_stats_impl(aes_server* s, aes_serve_stats* st)
     if (s == nullptr || st == nullptr)
         return AES_EINVAL;
     std::lock_guard<std::mutex> g(s->mu);
-    st->batches = (uint64_t)s->batches;
+    st->batches = s->batches.load(std::memory_order_relaxed);
     st->max_device_bytes_in_use = s->max_in_use.load(std::memory_order_relaxed);
     st->arena_blocks_in_use = s->arena_used_pub.load(std::memory_order_relaxed);
     st->pending = s->pending_pub.load(std::memory_order_relaxed) + s->incoming.size();

@@ -258,6 +258,7 @@ def test_pipe_config_checks_before_any_device_call():
     assert create(nslots=0) == aes.AES_EINVAL
     assert create(nslots=aes.AES_PIPE_MAX_SLOTS + 1) == aes.AES_EINVAL
     assert create(dev_bytes=(1 << 20) - 16) == aes.AES_EINVAL
+    assert create(chunk_bytes=1 << 62) == aes.AES_EINVAL  # 4 slots: the workspace size would wrap to 0
     assert create(dev=None) == aes.AES_EINVAL
     assert create(pinned_bytes=1 << 19) == aes.AES_EINVAL
     assert create(dev=A + 8) == aes.AES_EALIGN

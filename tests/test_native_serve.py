@@ -97,6 +97,37 @@ def test_dry_run_rejects_a_request_larger_than_one_batch():
                                       aes.AES_SERVED_DONE]
 
 
+def test_dry_run_release_frees_only_outputs_still_held():
+    """A second release of the same outputs, or a range the engine never
+    handed out, is refused (AES_EINVAL) and leaves the arena intact."""
+    srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=4000, budget_bytes=1 << 30, chunk_blocks=128,
+                     max_batch_items=64, nslots=2, auto_release=False, dry_run=True, dry_run_seconds=0.0002)
+    r = requests(10, 6, max_blocks=300, pool_blocks=100000, slots=2)
+    srv.submit(r)
+    out = wait_all(srv, 10)
+    assert (out["status"] == aes.AES_SERVED_DONE).all()
+    forged = out[:2].copy()
+    forged[0]["out_block"] = 10**9        # never handed out
+    forged[1]["nblocks"] += 1             # not the range that was handed out
+    with pytest.raises(aes.AesError):
+        srv.release(forged)
+    srv.release(out)
+    with pytest.raises(aes.AesError):
+        srv.release(out[:3])              # released already
+    t0 = time.time()
+    while srv.stats()["arena_blocks_in_use"] != 0:
+        assert time.time() - t0 < 5
+        time.sleep(0.001)
+    # every block of the arena is free again: a request as large as the arena runs
+    big = requests(1, 7, max_blocks=100, pool_blocks=100000, slots=2)
+    big[0]["in_block"] = 0
+    big[0]["nblocks"] = 4000
+    srv.submit(big)
+    got = wait_all(srv, 1)
+    srv.close()
+    assert got[0]["status"] == aes.AES_SERVED_DONE and got[0]["out_block"] == 0
+
+
 def test_dry_run_manual_release_gates_the_arena():
     srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=2000, budget_bytes=1 << 30, chunk_blocks=128,
                      max_batch_items=64, nslots=2, auto_release=False, dry_run=True, dry_run_seconds=0.0002)
