@@ -28,10 +28,10 @@ def _runtime(name):
     return found[-1] if found else None
 
 
-def _build_host_library(tmp_path, flags, name):
+def _build_host_library(tmp_path, flags, name, sources=HOST_SOURCES):
     from paper_1902_05234_amd import build
     objs = []
-    for src in HOST_SOURCES:
+    for src in sources:
         obj = str(tmp_path / (os.path.splitext(os.path.basename(src))[0] + ".o"))
         cmd = [build.hipcc(), "-std=c++17", "-fPIC", "-O1", "-g", "-x", "hip", "--cuda-host-only", *flags,
                "-I" + build.INCLUDE, "-I" + CSRC, "-c", src, "-o", obj]
@@ -44,15 +44,20 @@ def _build_host_library(tmp_path, flags, name):
     return lib
 
 
-def _run_tests(tmp_path, lib, runtime, options, test_files):
+def _run_child(tmp_path, lib, runtime, options, test_args):
     logs = str(tmp_path / "report")  # the runtimes write here: the child's own stderr is captured by its pytest
     env = dict(os.environ, AESGPU_LIBRARY=lib, LD_PRELOAD=runtime)
     for var, opts in options.items():
         env[var] = opts + ":log_path=" + logs
-    tests = [os.path.join(ROOT, "tests", f) for f in test_files]
     out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu", "-p", "no:cacheprovider",
-                          *tests], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                          *test_args], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     report = "".join(open(f).read() for f in sorted(glob.glob(logs + "*")))
+    return out, report
+
+
+def _run_tests(tmp_path, lib, runtime, options, test_files):
+    out, report = _run_child(tmp_path, lib, runtime, options,
+                             [os.path.join(ROOT, "tests", f) for f in test_files])
     assert out.returncode == 0 and not report, report[:4000] or (out.stdout[-3000:], out.stderr[-3000:])
     assert " passed" in out.stdout
 
@@ -74,3 +79,25 @@ def test_serving_engine_under_thread_sanitizer(tmp_path):
         pytest.skip("no clang ThreadSanitizer runtime in the ROCm toolchain")
     lib = _build_host_library(tmp_path, ["-Xarch_host", "-fsanitize=thread"], "libaesgpu_host_tsan.so")
     _run_tests(tmp_path, lib, runtime, {"TSAN_OPTIONS": "halt_on_error=1"}, ("test_native_serve.py",))
+
+
+def test_address_sanitizer_reports_a_planted_planner_overflow(tmp_path):
+    """The harness above can fail: a copy of the C ABI whose batch planner
+    writes each item one slot further on runs past the end of the item array
+    the binding allocated, and the report names the planner."""
+    runtime = _runtime("asan")
+    if runtime is None:
+        pytest.skip("no clang AddressSanitizer runtime in the ROCm toolchain")
+    src = open(os.path.join(CSRC, "aes_abi.cpp")).read()
+    good = "aes_work_item& it = items[m.decrypt ? id++ : ie++];"
+    assert src.count(good) == 1
+    planted = tmp_path / "aes_abi.cpp"
+    planted.write_text(src.replace(good, "aes_work_item& it = items[(m.decrypt ? id++ : ie++) + 1];"))
+    sources = [str(planted)] + [f for f in HOST_SOURCES if not f.endswith("aes_abi.cpp")]
+    lib = _build_host_library(tmp_path, SANITIZE, "libaesgpu_planted.so", sources)
+    out, report = _run_child(tmp_path, lib, runtime,
+                             {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                              "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"},
+                             [os.path.join(ROOT, "tests", "test_host_abi.py"), "-k", "batch_plan_covers"])
+    assert out.returncode != 0
+    assert "heap-buffer-overflow" in report and "aes_batch_plan" in report, report[:3000]
