@@ -217,8 +217,8 @@ def _crypt(fn, rk, nr, inp, out, nblocks, stream):
     n_in = _blocks_of(inp, "in")
     n_out = _blocks_of(out, "out")
     nblocks = n_in if nblocks is None else int(nblocks)
-    if nblocks > n_in or nblocks > n_out:
-        raise ValueError("nblocks=%d exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
+    if nblocks < 0 or nblocks > n_in or nblocks > n_out:
+        raise ValueError("nblocks=%d is negative or exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
     rk = _u32_array(rk, 4 * (int(nr) + 1))
     _check(fn(rk.ctypes.data_as(_u32p), int(nr), inp.data_ptr(), out.data_ptr(), nblocks, _stream_handle(stream)))
     return out
@@ -274,8 +274,8 @@ def aes_ctr_crypt_variant(rk, nr: int, iv: bytes, block_offset: int, inp, out, v
 def _cbc(fn, rk, nr, iv, inp, out, nblocks, stream, *extra):
     n_in, n_out = _blocks_of(inp, "in"), _blocks_of(out, "out")
     nblocks = n_in if nblocks is None else int(nblocks)
-    if nblocks > n_in or nblocks > n_out:
-        raise ValueError("nblocks=%d exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
+    if nblocks < 0 or nblocks > n_in or nblocks > n_out:
+        raise ValueError("nblocks=%d is negative or exceeds a buffer (in %d, out %d blocks)" % (nblocks, n_in, n_out))
     iv = bytes(iv)
     if len(iv) != 16:
         raise ValueError("the initialisation vector is 16 bytes, got %d" % len(iv))

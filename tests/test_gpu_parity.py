@@ -107,6 +107,10 @@ def test_empty_and_rejected_inputs():
     with pytest.raises(aes.AesError) as e:
         aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x[:48], x[16:64])
     assert e.value.code == aes.AES_EINVAL
+    with pytest.raises(ValueError):
+        aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, x, x, nblocks=-1)
+    with pytest.raises(ValueError):
+        aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, bytes(16), x[:32], x[32:], nblocks=-2)
     torch.cuda.synchronize()
 
 
