@@ -40,8 +40,12 @@ BUCKET_SIZES = ((2 << 10, 4 << 10), (16 << 10, 64 << 10), (256 << 10, 1 << 20, 2
 
 
 def source_hash() -> str:
+    """Hash of the device code the timings depend on (the .hip and .hpp
+    sources; host-only files and caches are left out)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "*"))):
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 

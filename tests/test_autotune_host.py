@@ -33,3 +33,15 @@ def test_bucket_winner_ignores_variants_missing_at_some_size():
     }
     w = autotune.bucket_winner(per_size)
     assert (w["bpt"], w["wg"], w["placement"]) == (1, 512, 2)
+
+
+def test_source_hash_covers_device_sources_only():
+    """The record's source hash reads the .hip/.hpp files and ignores
+    anything else under csrc (a __pycache__ directory, host-only sources)."""
+    import os
+    from paper_1902_05234_amd import autotune
+    csrc = os.path.join(os.path.dirname(autotune.__file__), "csrc")
+    os.makedirs(os.path.join(csrc, "__pycache__"), exist_ok=True)
+    h = autotune.source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    assert autotune.source_hash() == h
