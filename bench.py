@@ -11,7 +11,8 @@ before timing starts.  Prints ONE JSON line:
   roofline     the encrypt kernel against the LDS lookup roof (the binding
                unit: 16 table lookups per block per round), with the HBM and
                VALU roofs beside it, the HBM bytes rocprofv3 counted, and the
-               engine clock and socket power held under load
+               engine clock, socket power and encryption rate held over 2 s
+               of back-to-back load
   cpu_baseline the CPU oracle (byte-wise FIPS-197, all host cores) on a
                bounded slice of the same workload
   batched      20,000 mixed messages in one persistent launch (graph replay)
@@ -267,13 +268,22 @@ def clock_under_load(torch, aes, b, seconds=2.0):
     ks = aes.aes_expand_key(b["key"])
     th = threading.Thread(target=sample)
     th.start()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    launches = 0
     t0 = time.perf_counter()
+    ev0.record()
     while time.perf_counter() - t0 < seconds:
         for _ in range(10):
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, b["x"], b["c"])
+        launches += 10
         torch.cuda.synchronize()
+    ev1.record()
+    torch.cuda.synchronize()
     stop.set()
     th.join()
+    # throughput over the whole window (the host syncs every 10 launches, a
+    # gap of microseconds per ~7 ms): the rate the clock settles at
+    sustained = launches * b["x"].numel() / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     clks = [c for c, _ in samples[1:] if c]
     pws = [p for _, p in samples[1:] if p]
     if not clks:
@@ -281,6 +291,7 @@ def clock_under_load(torch, aes, b, seconds=2.0):
     mhz = sum(clks) / len(clks)
     return {"sclk_MHz": round(mhz), "socket_power_W": round(sum(pws) / len(pws)) if pws else None,
             "samples": len(clks), "lds_roof_at_clock_Glookup_s": round(LDS_PEAK / 1e9 * mhz * 1e6 / MI355X_CLOCK_HZ, 1),
+            "encrypt_GB_s": round(sustained, 1), "launches": launches,
             "what": "bulk AES-128 encryption of 1 GiB back to back for %.0f s after the timed steps" % seconds}
 
 
