@@ -29,6 +29,25 @@ def test_library_exports_every_header_symbol():
     assert set(names) == set(aes.exported_symbols())
 
 
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as pedantic C99 (C callers need no C++)
+    and as C++17, with no warnings."""
+    import shutil
+    import subprocess
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "aesgpu.h"\n'
+                   "int main(void) { aes_msg m; aes_work_item w; aes_variant v; (void)m; (void)w; (void)v;\n"
+                   "  const char *(*err)(void) = aes_last_error; (void)err;\n"
+                   "  return AES_MAX_ITEM_BLOCKS > 0 ? 0 : 1; }\n")
+    for cc, lang, std in (("gcc", "c", "-std=c99"), ("g++", "c++", "-std=c++17")):
+        if shutil.which(cc) is None:
+            pytest.skip("%s not installed" % cc)
+        r = subprocess.run([cc, std, "-x", lang, "-Wall", "-Wextra", "-pedantic", "-Werror",
+                            "-I" + os.path.dirname(HEADER), "-c", str(src), "-o", str(tmp_path / "o.o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, (cc, r.stderr[-2000:])
+
+
 def le_words(b: bytes) -> np.ndarray:
     return np.frombuffer(b, dtype="<u4").astype(np.uint32)
 
