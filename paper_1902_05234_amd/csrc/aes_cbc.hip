@@ -123,7 +123,7 @@ hipError_t launch_cbc_decrypt(const LaunchShape& shape, int placement, int nr, c
     const uint4 iv = make_uint4(w[0], w[1], w[2], w[3]);
     switch (placement) {
     case kPlace4: return launch_cbc_bpt<kPlace4>(nr, in, out, nblocks, iv, rk, shape, cus, stream);
-    case kPlace2: return launch_cbc_bpt<kPlace2>(nr, in, out, nblocks, iv, rk, shape, cus, stream);
+    case kPlace2: return launch_cbc_bpt<kPlace2>(nr, in, out, nblocks, iv, inner_keys_rotr8(rk, nr), shape, cus, stream);
     case kPlace1: return launch_cbc_bpt<kPlace1>(nr, in, out, nblocks, iv, rk, shape, cus, stream);
     default: return hipErrorInvalidValue;
     }

@@ -128,7 +128,7 @@ hipError_t launch_ctr(const LaunchShape& shape, int placement, int nr, const voi
 {
     switch (placement) {
     case kPlace4: return launch_ctr_bpt<kPlace4>(nr, in, out, nbytes, c0, rk, shape, cus, stream);
-    case kPlace2: return launch_ctr_bpt<kPlace2>(nr, in, out, nbytes, c0, rk, shape, cus, stream);
+    case kPlace2: return launch_ctr_bpt<kPlace2>(nr, in, out, nbytes, c0, inner_keys_rotr8(rk, nr), shape, cus, stream);
     case kPlace1: return launch_ctr_bpt<kPlace1>(nr, in, out, nbytes, c0, rk, shape, cus, stream);
     default: return hipErrorInvalidValue;
     }

@@ -282,8 +282,11 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
             if (PL == kPlace4) {
                 w[j] = xor3_key(xor3(a, b, c), d, k);
             } else if (PL == kPlace2) {
-                // a: T0, c: T2 as stored; b, d need T1 = rotl8(T0), T3 = rotl8(T2)
-                w[j] = xor3_key(a, c, k) ^ rotl8(b ^ d);
+                // a: T0, c: T2 as stored; b, d need T1 = rotl8(T0), T3 = rotl8(T2).
+                // The key joins b and d before the rotate, so these kernels take
+                // each inner-round key word turned right by 8 bits
+                // (inner_keys_rotr8): three VALU instructions per column.
+                w[j] = xor3(a, c, rotl8(xor3_key(b, d, k)));
             } else {
                 // all from T0: a ^ rotl8(b) ^ rotl16(c) ^ rotl24(d)
                 w[j] = xor3_key(a, rotl8(b ^ rotl8(c ^ rotl8(d))), k);

@@ -139,9 +139,10 @@ template <int PL>
 hipError_t launch_placement(const LaunchShape& shape, int nr, bool decrypt, const void* in, void* out,
                             uint64_t nblocks, const RoundKeys& rk, int cus, hipStream_t stream)
 {
+    const RoundKeys k = PL == kPlace2 ? inner_keys_rotr8(rk, nr) : rk;
     if (decrypt)
-        return launch_bpt<true, PL>(nr, in, out, nblocks, rk, shape, cus, stream);
-    return launch_bpt<false, PL>(nr, in, out, nblocks, rk, shape, cus, stream);
+        return launch_bpt<true, PL>(nr, in, out, nblocks, k, shape, cus, stream);
+    return launch_bpt<false, PL>(nr, in, out, nblocks, k, shape, cus, stream);
 }
 
 }  // namespace aesgpu

@@ -15,6 +15,17 @@ struct RoundKeys {
     uint32_t w[60];
 };
 
+// The 2-table kernels add an inner round's key to the two lookups that are
+// rotated left by 8 bits afterwards, so they take words 4 .. 4*nr-1 of the
+// schedule rotated right by 8 bits; the first and last round keys are as is.
+inline RoundKeys inner_keys_rotr8(const RoundKeys& rk, int nr)
+{
+    RoundKeys r = rk;
+    for (int i = 4; i < 4 * nr && i < 60; ++i)
+        r.w[i] = (r.w[i] >> 8) | (r.w[i] << 24);
+    return r;
+}
+
 struct LaunchShape {
     int bpt;   // blocks per thread per iteration: 1, 2, 4
     int wg;    // workgroup size (multiple of 64, at most 1024)
