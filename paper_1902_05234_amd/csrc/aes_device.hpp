@@ -96,6 +96,8 @@ __device__ __forceinline__ uint32_t shl16(uint32_t a)
 }
 
 __device__ __forceinline__ uint32_t rotl8(uint32_t y) { return (y << 8) | (y >> 24); }
+__device__ __forceinline__ uint32_t rotl16(uint32_t y) { return (y << 16) | (y >> 16); }
+__device__ __forceinline__ uint32_t rotl24(uint32_t y) { return (y << 24) | (y >> 8); }
 
 __device__ __forceinline__ uint32_t lds_word(const uint32_t* lds, uint32_t byte_addr)
 {
@@ -288,8 +290,9 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
                 // (inner_keys_rotr8): three VALU instructions per column.
                 w[j] = xor3(a, c, rotl8(xor3_key(b, d, k)));
             } else {
-                // all from T0: a ^ rotl8(b) ^ rotl16(c) ^ rotl24(d)
-                w[j] = xor3_key(a, rotl8(b ^ rotl8(c ^ rotl8(d))), k);
+                // all from T0: a ^ rotl8(b) ^ rotl16(c) ^ rotl24(d), three
+                // independent rotates and two XOR3s (five VALU per column)
+                w[j] = xor3_key(xor3(a, rotl8(b), rotl16(c)), rotl24(d), k);
             }
         }
     }
