@@ -294,7 +294,9 @@ typedef struct {
  *   items_dev:     device copy of the planned items (n_enc + n_dec entries).
  *   key_table_dev: device key table of n_slots slots.
  *   in_base/out_base: device arenas of in_blocks / out_blocks blocks, 16-byte
- *                  aligned; the same arena for both is allowed (in place).
+ *                  aligned; the same arena for both is allowed (in place),
+ *                  any other overlap of [in_base, +16*in_blocks) and
+ *                  [out_base, +16*out_blocks) is refused (AES_EINVAL).
  *   counters_dev:  device array of 4 uint32, all zero before the first launch:
  *                  [0],[1] claim counters, [2] finished workgroups (the last
  *                  workgroup resets [0..2] to zero, so the launch can be

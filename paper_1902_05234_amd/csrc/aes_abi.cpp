@@ -270,6 +270,54 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     return AES_OK;
 }
 
+// Arguments of one batch launch, checked; the caller supplies the counters.
+struct BatchLaunch {
+    BatchArgs args;
+    int bpt, wg, grid;
+};
+
+int check_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, const uint32_t* key_table_dev,
+                size_t n_slots, const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks,
+                const aes_batch_config* cfg, BatchLaunch* out)
+{
+    if (n_enc > UINT32_MAX || n_dec > UINT32_MAX - n_enc || n_slots > UINT32_MAX)
+        return fail(AES_ERANGE, "work list or key table too large");
+    if (items_dev == nullptr || key_table_dev == nullptr || in_base == nullptr || out_base == nullptr)
+        return fail(AES_EINVAL, "null pointer argument");
+    if ((reinterpret_cast<uintptr_t>(in_base) | reinterpret_cast<uintptr_t>(out_base)) & 15u)
+        return fail(AES_EALIGN, "in/out arenas must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(items_dev) & 7u) || (reinterpret_cast<uintptr_t>(key_table_dev) & 3u))
+        return fail(AES_EALIGN, "work list / key table / counters misaligned");
+    if (in_blocks > (SIZE_MAX >> 5) || out_blocks > (SIZE_MAX >> 5))
+        return fail(AES_EINVAL, "arena sizes too large (%zu / %zu blocks)", in_blocks, out_blocks);
+    // Each arena with its own length: only the very same arena (in place) may
+    // be shared; any other overlap would let items read blocks others write.
+    const uintptr_t ib = reinterpret_cast<uintptr_t>(in_base), ob = reinterpret_cast<uintptr_t>(out_base);
+    if (ib != ob && ib < ob + (uint64_t)out_blocks * 16u && ob < ib + (uint64_t)in_blocks * 16u)
+        return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
+    aes_batch_config c{1, 1024, 0, -1};
+    if (cfg)
+        c = *cfg;
+    if (c.bpt != 1 && c.bpt != 2 && c.bpt != 4)
+        return fail(AES_EINVAL, "bpt must be 1, 2 or 4, got %d", c.bpt);
+    if (c.wg < 64 || c.wg > 1024 || c.wg % 64)
+        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", c.wg);
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    int grid = 0, enc_groups = 0;
+    // the item counts stand in for the byte shares (the items live on the device)
+    batch_grid(n_enc, n_dec, n_enc, n_enc + n_dec, c.wg, c.grid > 0 ? c.grid : cus, c.enc_groups, &grid,
+               &enc_groups);
+    out->args = BatchArgs{reinterpret_cast<const WorkItem*>(items_dev), (uint32_t)n_enc, (uint32_t)n_dec,
+                          key_table_dev, (uint32_t)n_slots, in_base, out_base, (uint64_t)in_blocks,
+                          (uint64_t)out_blocks, nullptr, (uint32_t)enc_groups};
+    out->bpt = c.bpt;
+    out->wg = c.wg;
+    out->grid = grid;
+    return AES_OK;
+}
+
 }  // namespace
 
 int device_cu_count()
@@ -495,36 +543,17 @@ int aes_ecb_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, co
 {
     if (n_enc + n_dec == 0)
         return AES_OK;
-    if (n_enc + n_dec > UINT32_MAX || n_slots > UINT32_MAX)
-        return fail(AES_ERANGE, "work list or key table too large");
-    if (items_dev == nullptr || key_table_dev == nullptr || counters_dev == nullptr || in_base == nullptr ||
-        out_base == nullptr)
+    if (counters_dev == nullptr)
         return fail(AES_EINVAL, "null pointer argument");
-    if ((reinterpret_cast<uintptr_t>(in_base) | reinterpret_cast<uintptr_t>(out_base)) & 15u)
-        return fail(AES_EALIGN, "in/out arenas must be 16-byte aligned");
-    if ((reinterpret_cast<uintptr_t>(items_dev) & 7u) || (reinterpret_cast<uintptr_t>(key_table_dev) & 3u) ||
-        (reinterpret_cast<uintptr_t>(counters_dev) & 3u))
+    if (reinterpret_cast<uintptr_t>(counters_dev) & 3u)
         return fail(AES_EALIGN, "work list / key table / counters misaligned");
-    if (ranges_partially_overlap(in_base, out_base, (uint64_t)std::min(in_blocks, out_blocks) * 16u))
-        return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
-    aes_batch_config c{1, 1024, 0, -1};
-    if (cfg)
-        c = *cfg;
-    if (c.bpt != 1 && c.bpt != 2 && c.bpt != 4)
-        return fail(AES_EINVAL, "bpt must be 1, 2 or 4, got %d", c.bpt);
-    if (c.wg < 64 || c.wg > 1024 || c.wg % 64)
-        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", c.wg);
-    int cus = device_cu_count();
-    if (cus <= 0)
-        return fail(AES_EHIP, "cannot query the current HIP device");
-    int grid = 0, enc_groups = 0;
-    // the item counts stand in for the byte shares (the items live on the device)
-    batch_grid(n_enc, n_dec, n_enc, n_enc + n_dec, c.wg, c.grid > 0 ? c.grid : cus, c.enc_groups, &grid,
-               &enc_groups);
-    BatchArgs a{reinterpret_cast<const WorkItem*>(items_dev), (uint32_t)n_enc, (uint32_t)n_dec, key_table_dev,
-                (uint32_t)n_slots, in_base, out_base, (uint64_t)in_blocks, (uint64_t)out_blocks, counters_dev,
-                (uint32_t)enc_groups};
-    hipError_t e = launch_batch(a, c.bpt, grid, c.wg, static_cast<hipStream_t>(stream));
+    BatchLaunch b;
+    int rc = check_batch(items_dev, n_enc, n_dec, key_table_dev, n_slots, in_base, in_blocks, out_base, out_blocks,
+                         cfg, &b);
+    if (rc != AES_OK)
+        return rc;
+    b.args.counters = counters_dev;
+    hipError_t e = launch_batch(b.args, b.bpt, b.grid, b.wg, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "batch kernel launch");
     return AES_OK;

@@ -323,6 +323,27 @@ def test_batch_launch_checks():
     assert lib.aes_ecb_batch(0x1000, 1, 0, 0x1000, 1, 0x2000, 1, 0x3000, 1, 0x4000, aes.ctypes.byref(cfg), None) == aes.AES_EINVAL
 
 
+def test_batch_arena_overlap_uses_each_arenas_own_length():
+    """An output arena inside a larger input arena (beyond the smaller
+    arena's length from the start) is refused; the very same arena (in
+    place) is allowed whatever the two lengths.  A bad bpt stops every
+    accepted case before any device call."""
+    lib = aes._lib()
+    cfg = aes._BatchConfig(5, 1024, 0, -1)
+    base = 0x100000
+    cases = [
+        (base, 1000, base + 16 * 500, 10, True),    # out lies inside in, past 10 blocks from the start
+        (base + 16 * 500, 10, base, 1000, True),    # in lies inside out
+        (base, 1000, base + 16 * 999, 10, True),    # overlap of one block at the end of in
+        (base, 1000, base + 16 * 1000, 10, False),  # adjacent: no overlap
+        (base, 1000, base, 10, False),              # the same arena, in place
+    ]
+    for ib, nin, ob, nout, overlap in cases:
+        rc = lib.aes_ecb_batch(0x1000, 1, 0, 0x1000, 1, ib, nin, ob, nout, 0x4000, aes.ctypes.byref(cfg), None)
+        assert rc == aes.AES_EINVAL
+        assert ("overlap" in aes.aes_last_error()) == overlap, (ib, nin, ob, nout, aes.aes_last_error())
+
+
 # --------------------------------------------------------------- batch planner
 def make_msgs(nblocks, decrypt, slots=None):
     m = np.zeros(len(nblocks), dtype=aes.MSG_DTYPE)
