@@ -261,11 +261,15 @@ void worker_loop(aes_server* s)
     if (!s->cfg.dry_run)
         hipSetDevice(s->device);
     uint64_t seen = 0;
+    // The head of the queue could not be admitted while no slot was busy:
+    // only a release by the caller (or a stop) can change that, so the
+    // worker sleeps until one arrives instead of retrying.
+    bool blocked = false;
     for (;;) {
         bool stopping;
-        const bool idle = s->pending.empty() && std::none_of(s->slots.begin(), s->slots.end(),
-                                                             [](const Slot& x) { return x.busy; });
-        if (idle) {
+        const bool idle = (s->pending.empty() || blocked) &&
+                          std::none_of(s->slots.begin(), s->slots.end(), [](const Slot& x) { return x.busy; });
+        if (idle && !blocked) {
             // spin briefly before sleeping: a request arriving within ~50 us
             // is picked up without a thread wake-up
             const auto until = Clock::now() + std::chrono::microseconds(50);
@@ -275,7 +279,7 @@ void worker_loop(aes_server* s)
         {
             std::unique_lock<std::mutex> g(s->mu);
             if (idle && s->incoming.empty() && s->releases.empty() && !s->stop)
-                s->cv.wait_for(g, std::chrono::microseconds(200));
+                s->cv.wait_for(g, std::chrono::microseconds(blocked ? 2000 : 200));
             seen = s->submitted.load(std::memory_order_acquire);
             while (!s->incoming.empty()) {
                 s->pending.push_back(s->incoming.front());
@@ -339,6 +343,23 @@ void worker_loop(aes_server* s)
             if (s->in_use > s->max_in_use.load(std::memory_order_relaxed))
                 s->max_in_use.store(s->in_use, std::memory_order_relaxed);
             launch(s, sl, batch);
+        }
+        const bool none_busy =
+            std::none_of(s->slots.begin(), s->slots.end(), [](const Slot& x) { return x.busy; });
+        blocked = !s->pending.empty() && none_busy;
+        if (stopping && blocked) {
+            // Nothing is running, so the budget is free and the head waits
+            // for output space that the caller still holds (manual release);
+            // the caller is inside aes_server_destroy and releases nothing
+            // more, so the queued requests are finished as rejected.
+            std::lock_guard<std::mutex> g(s->mu);
+            for (Req* q : s->pending) {
+                q->status = AES_SERVED_REJECTED;
+                q->done = s->now();
+                s->completed.push_back(q);
+            }
+            s->pending.clear();
+            blocked = false;
         }
         s->arena_used_pub.store(s->arena.used(), std::memory_order_relaxed);
         s->pending_pub.store(s->pending.size(), std::memory_order_relaxed);

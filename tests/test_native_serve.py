@@ -148,6 +148,49 @@ def test_dry_run_manual_release_gates_the_arena():
     assert len(done) == 30
 
 
+CLOSE_WHILE_BLOCKED = r"""
+import sys, time
+import numpy as np
+from paper_1902_05234_amd import aes
+srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=1000, budget_bytes=1 << 30, chunk_blocks=128,
+                 max_batch_items=64, nslots=2, auto_release=False, dry_run=True, dry_run_seconds=0.0002)
+r = np.zeros(3, dtype=aes.REQUEST_DTYPE)
+r["nblocks"] = 600
+r["in_block"] = [0, 1000, 2000]
+srv.submit(r)
+got, t0 = [], time.time()
+while not got:
+    got = srv.poll().tolist()
+    assert time.time() - t0 < 10, "the first request did not finish"
+    time.sleep(0.001)
+time.sleep(0.05)
+# the second request waits for output space the caller holds: the worker must sleep, not spin
+c0, w0 = time.process_time(), time.time()
+time.sleep(0.5)
+cpu = (time.process_time() - c0) / (time.time() - w0)
+st = srv.stats()
+srv.close()
+print("closed", cpu, st["pending"], flush=True)
+"""
+
+
+def test_dry_run_close_with_held_outputs_and_a_blocked_request():
+    """Without auto release, a request that waits for output space the
+    caller still holds neither keeps the worker busy nor stops close():
+    close() finishes it as rejected and returns."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", CLOSE_WHILE_BLOCKED], cwd=root, capture_output=True, text=True,
+                       timeout=60, env=dict(os.environ, PYTHONPATH=root))
+    assert r.returncode == 0, r.stderr[-2000:]
+    words = r.stdout.split()
+    assert words[0] == "closed"
+    assert float(words[1]) < 0.5, "the engine's worker spins while the queue is blocked"
+    assert int(words[2]) == 2
+
+
 def test_create_rejects_bad_configs():
     for kw in (dict(nslots=0), dict(nslots=17), dict(chunk_blocks=0), dict(chunk_blocks=aes.AES_MAX_ITEM_BLOCKS + 1),
                dict(bpt=3), dict(wg=100), dict(budget_bytes=0), dict(max_batch_items=0)):
