@@ -388,7 +388,10 @@ int aes_server_poll(aes_server *s, aes_served *out, size_t cap, size_t *n);
  * out) are skipped, and the call returns AES_EINVAL; the others are freed. */
 int aes_server_release(aes_server *s, const aes_served *done, size_t n);
 int aes_server_stats(aes_server *s, aes_serve_stats *stats);
-/* Finishes every submitted request, then frees the engine (not the buffers). */
+/* Finishes every submitted request, then frees the engine (not the buffers).
+ * Without auto_release, queued requests that cannot get output space while
+ * nothing runs (the caller still holds outputs and, being inside this call,
+ * releases no more) are finished as AES_SERVED_REJECTED instead of waiting. */
 int aes_server_destroy(aes_server *s);
 /* Open-loop replay on an auto_release server: request i is submitted at
  * arrival_s[i] seconds after the call starts; returns when all have finished,
