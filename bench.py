@@ -31,7 +31,8 @@ before timing starts.  Prints ONE JSON line:
                served requests checked against each request run alone
 
 Flags: --gpus N (only 1 is supported), --steps K (default 100), --warmup W
-(default 30), --no-batch / --no-sweep / --no-cpu / --no-host / --no-serve to
+(default 30) plus --warmup-seconds S (default 1: warm-up continues until S
+seconds of back-to-back steps have passed), --no-batch / --no-sweep / --no-cpu / --no-host / --no-serve to
 skip sections, --profile to run only a few bulk and copy launches (for
 rocprofv3).
 """
@@ -155,12 +156,24 @@ def bulk(torch, aes, inputs, args):
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, c)
             aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, c, p)
 
-    for _ in range(args.warmup):
-        step(False)
+    # Warm-up: at least --warmup steps, then more back-to-back steps until
+    # --warmup-seconds of load have passed.  The engine clock ramps up from
+    # idle and then settles under sustained load over a few hundred ms, so a
+    # count of steps alone (a few ms at 1 GiB) would time the ramp.  The host
+    # syncs every 10 steps only to read the clock.
+    tw = time.perf_counter()
+    warm_steps = 0
+    while warm_steps < args.warmup or time.perf_counter() - tw < args.warmup_seconds:
+        for _ in range(10 if warm_steps >= args.warmup else 1):
+            step(False)
+            warm_steps += 1
+        if warm_steps >= args.warmup:
+            torch.cuda.synchronize()
     # The timed steps follow the warm-up directly: an idle gap would let the
     # engine clock settle again and the first timed launches would pay its
     # ramp.  The round trip is checked on the output of the timed steps.
     torch.cuda.synchronize()
+    warm_s = time.perf_counter() - tw
     gc.disable()  # no collector pause between launches inside the timed region
     try:
         t0 = time.perf_counter()
@@ -173,7 +186,14 @@ def bulk(torch, aes, inputs, args):
     if not torch.equal(p, x):
         raise RuntimeError("round trip failed on the 1 GiB buffer")
     enc_ms, dec_ms = t_enc.ms(), t_dec.ms()
-    return dict(key=key, x=x, c=c, nbytes=nbytes, elapsed=elapsed, enc_ms=enc_ms, dec_ms=dec_ms)
+    return dict(key=key, x=x, c=c, nbytes=nbytes, elapsed=elapsed, enc_ms=enc_ms, dec_ms=dec_ms,
+                warmup_steps=warm_steps, warmup_ms=warm_s * 1e3)
+
+
+def launch_stats(ms):
+    """Mean and median of per-launch durations (ms)."""
+    s = sorted(ms)
+    return {"mean_ms": round(sum(s) / len(s), 4), "median_ms": round(s[len(s) // 2], 4), "launches": len(s)}
 
 
 def roofline(b, traffic, aes):
@@ -181,11 +201,14 @@ def roofline(b, traffic, aes):
     v = aes.aes_tune_get(10, False, nblocks)
     places = {0: "4 tables", 1: "2 tables", 2: "1 table"}
     t = sum(b["enc_ms"]) / len(b["enc_ms"]) * 1e-3
+    td = sum(b["dec_ms"]) / len(b["dec_ms"]) * 1e-3
     nr = 10
     lookups = lookups_per_block(nr) * nblocks
     ach = lookups / t / 1e9
+    ach_d = lookups / td / 1e9
     peak = LDS_PEAK / 1e9
     hbm_alg = 32 * nblocks
+    vd = aes.aes_tune_get(10, True, nblocks)
     return {
         "kernel": "ecb_kernel<Nr=10, encrypt, %d B/thread, %s in LDS, %d-thread workgroups>" % (
             16 * v.bpt, places.get(v.placement, "?"), v.wg),
@@ -196,7 +219,11 @@ def roofline(b, traffic, aes):
         "frac": round(ach / peak, 4),
         "traffic": traffic,
         "per_launch": {"blocks": nblocks, "lookups": lookups, "hbm_bytes_algorithmic": hbm_alg,
-                       "avg_ms": round(t * 1e3, 4)},
+                       "avg_ms": round(t * 1e3, 4), **launch_stats(b["enc_ms"])},
+        "decrypt": {"kernel": "ecb_kernel<Nr=10, decrypt, %d B/thread, %s in LDS, %d-thread workgroups>" % (
+                        16 * vd.bpt, places.get(vd.placement, "?"), vd.wg),
+                    "achieved": round(ach_d, 1), "peak": round(peak, 1), "unit": "Glookup/s",
+                    "frac": round(ach_d / peak, 4), "avg_ms": round(td * 1e3, 4), **launch_stats(b["dec_ms"])},
         "roofs": {
             "lds": {"achieved_Glookup_s": round(ach, 1), "peak": round(peak, 1), "frac": round(ach / peak, 4)},
             "hbm": {"achieved_GB_s": round(hbm_alg / t / 1e9, 1), "peak": HBM_PEAK_BPS / 1e9,
@@ -369,16 +396,17 @@ GRAPH_LAUNCHES = 20
 
 
 WARM_SECONDS = 0.05  # the engine clock takes a few tens of ms of load to ramp up from idle
+WARM_SECONDS_LARGE = 0.25  # long launches: load long enough for the clock to settle, as in the bulk warm-up
 
 
-def warm(torch, fn):
+def warm(torch, fn, seconds=WARM_SECONDS):
     """Run fn back to back, with no synchronisation in between, for about
-    WARM_SECONDS before a timing (the timed launches are back to back too)."""
+    `seconds` before a timing (the timed launches are back to back too)."""
     t0 = time.perf_counter()
     fn()
     torch.cuda.synchronize()
     one = max(time.perf_counter() - t0, 1e-6)
-    for _ in range(max(1, min(4000, int(WARM_SECONDS / one)))):
+    for _ in range(max(1, min(4000, int(seconds / one)))):
         fn()
     torch.cuda.synchronize()
 
@@ -402,7 +430,7 @@ def launch_ms(torch, fn, n):
         ms = sorted(tm.ms())[2] / GRAPH_LAUNCHES
         del g
         return ms
-    warm(torch, fn)
+    warm(torch, fn, WARM_SECONDS_LARGE)
     reps = max(5, min(50, int(8 * GiB / n)))
     tm = Timer(torch)
     for _ in range(reps):
@@ -428,7 +456,7 @@ def sweep(torch, aes, inputs, sizes):
     xi, xo = buf_in[:n], buf_out[:n]
 
     def timed10(fn):
-        warm(torch, fn)
+        warm(torch, fn, WARM_SECONDS_LARGE)
         tm = Timer(torch)
         for _ in range(10):
             tm.run(fn)
@@ -689,11 +717,49 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     return res
 
 
+PROFILE_MID_SIZES = (64 << 10, MiB, 4 * MiB, 16 * MiB, 32 * MiB)
+
+
+def profile_mid(torch, aes, inputs, replays=10):
+    """Launches for a kernel trace of the mid-size regime: for each size, a
+    HIP graph of GRAPH_LAUNCHES back-to-back AES-128 encryptions with the
+    tuned default variant, warmed up and then replayed `replays` times; first
+    the same for a 16-byte device copy (the dispatch floor).  In the trace,
+    each kernel's duration and the gap to the next kernel of its graph split
+    the per-launch time into work inside the kernel and dispatch between
+    kernels."""
+    ks = aes.aes_expand_key(inputs.random_key(1, 128))
+    x = inputs.device_random_bytes(1, max(PROFILE_MID_SIZES))
+    y = torch.empty_like(x)
+    cases = [("copy 16 B", lambda: aes.aes_device_copy(x[:16], y[:16]))]
+    for n in PROFILE_MID_SIZES:
+        xi, yi = x[:n], y[:n]
+        cases.append(("AES-128 encrypt %s %s" % (size_name(n) if n >= MiB else "%dKiB" % (n >> 10),
+                                                 aes.aes_tune_get(10, False, n // 16)),
+                      lambda xi=xi, yi=yi: aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, xi, yi)))
+    for name, fn in cases:
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(GRAPH_LAUNCHES):
+                fn()
+        warm(torch, g.replay)
+        tm = Timer(torch)
+        for _ in range(replays):
+            tm.run(g.replay)
+        ms = sorted(tm.ms())[replays // 2] / GRAPH_LAUNCHES
+        del g
+        log("%s: %.2f us per launch (graph replay, events)" % (name, ms * 1e3))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--warmup-seconds", type=float, default=1.0,
+                    help="after --warmup steps, keep warming up until this much load has passed")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -702,7 +768,9 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host-inclusive file-size sweep")
     ap.add_argument("--serve-levels", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9,1.0")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--profile", action="store_true", help="only a few copy and bulk launches (for rocprofv3)")
+    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid"), default=None,
+                    help="bulk: only a few copy and 1 GiB launches; mid: graph-replayed AES-128 encryptions of "
+                         "64 KiB ... 32 MiB and of a 16-byte copy (for rocprofv3 kernel traces)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -721,6 +789,9 @@ def main():
     props = torch.cuda.get_device_properties(0)
     log("device:", props.name, "CUs:", props.multi_processor_count)
 
+    if args.profile == "mid":
+        profile_mid(torch, aes, inputs)
+        return
     if args.profile:
         x = inputs.device_random_bytes(1, GiB)
         y = torch.empty_like(x)
@@ -746,6 +817,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": b["warmup_steps"],
+        "warmup_ms": round(b["warmup_ms"], 1),
         "ms_per_step": round(b["elapsed"] / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",

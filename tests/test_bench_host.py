@@ -44,3 +44,9 @@ def test_roofline_object(bench):
     assert r["frac"] == pytest.approx(lookups / t / bench.LDS_PEAK, abs=1e-4)
     assert r["roofs"]["hbm"]["achieved_GB_s"] == pytest.approx(32 * nblocks / t / 1e9, rel=1e-3)
     assert r["roofs"]["payload_roof_GB_s"] == pytest.approx(bench.LDS_PEAK * 16 / 160 / 1e9, rel=1e-3)
+    # decryption is reported beside encryption, with the same lookups per block
+    td = 0.73e-3
+    assert r["decrypt"]["achieved"] == pytest.approx(lookups / td / 1e9, rel=1e-3)
+    assert r["decrypt"]["frac"] == pytest.approx(lookups / td / bench.LDS_PEAK, abs=1e-4)
+    assert r["per_launch"]["mean_ms"] == pytest.approx(0.72) and r["per_launch"]["median_ms"] == 0.72
+    assert r["per_launch"]["launches"] == 3 and r["decrypt"]["launches"] == 1
