@@ -114,7 +114,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict_
                                                      uint4* __restrict__ out_base, uint64_t in_blocks,
                                                      uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups)
 {
-    __shared__ uint32_t lds[Layout<kPlace4, true>::words];
+    __shared__ __align__(16) uint32_t lds[Layout<kPlace4, true>::words];
     bool dec = blockIdx.x >= enc_groups;
     for (int pass = 0; pass < 2; ++pass, dec = !dec) {
         if ((dec ? n_dec : n_enc) == 0)

@@ -19,7 +19,7 @@ template <int NR, int BPT, int PL>
 __global__ __launch_bounds__(1024) void cbc_dec_kernel(const uint4* __restrict__ in, uint4* __restrict__ out,
                                                        uint64_t nblocks, uint4 iv, RoundKeys rk)
 {
-    __shared__ uint32_t lds[Layout<PL, true>::words];
+    __shared__ __align__(16) uint32_t lds[Layout<PL, true>::words];
     fill_tables<PL, true>(lds, &c_tables);
     __syncthreads();
     const LaneBases<PL, true> lb(threadIdx.x);

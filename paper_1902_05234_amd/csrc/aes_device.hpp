@@ -143,64 +143,62 @@ struct LaneBases {
 };
 
 // Fill the replicated tables of one direction into LDS (whole workgroup).
-// Consecutive lanes write consecutive words (no bank conflicts); each thread
-// first issues up to kFillBatch independent loads of source words and only
-// then writes, so a fill costs a couple of memory round trips, not one per
-// word.
-constexpr uint32_t kFillBatch = 16;
+// The fill is a list of jobs of 8 entries x 32 replicas: 32 jobs for the
+// T-table entries, then (decryption) 32 jobs for the word-wide InvS or 8 for
+// the byte-packed one (64 packed words).  In a job, lane l stores replicas
+// 4(l & 7) .. 4(l & 7) + 3 of entry 8 * job + (l >> 3) with one ds_write_b128
+// per stored table, the T-tables as rotations of the one loaded word
+// (T_t = rotl(T_0, 8t)); every 8 lanes store 128 consecutive bytes, so the
+// stores are conflict free.  A wave loads the source words of up to
+// kFillBatch jobs (one per lane per job) before its first store, so the
+// whole fill costs one memory round trip with workgroups of 256 threads or
+// more (512 or more for decryption) and holds few registers.
+constexpr uint32_t kFillBatch = 8;
+
+__device__ __forceinline__ void store4(uint32_t* lds, uint32_t word, uint32_t v)
+{
+    *reinterpret_cast<uint4*>(lds + word) = make_uint4(v, v, v, v);
+}
 
 template <int PL, bool kDecrypt>
 __device__ __forceinline__ void fill_tables(uint32_t* lds, const TableSet* __restrict__ tabs)
 {
     using L = Layout<PL, kDecrypt>;
+    constexpr uint32_t kTJobs = 32;
+    constexpr uint32_t kJobs = kTJobs + (!kDecrypt ? 0u : PL == kPlace4 ? 32u : 8u);
+    constexpr uint32_t kStride = PL == kPlace1 ? 32u : 64u;  // words from one T-table entry to the next
     const uint32_t* src = kDecrypt ? tabs->td0 : tabs->te0;
-    constexpr uint32_t n = L::table_bytes / 4;
-    const uint32_t step = blockDim.x;
-    for (uint32_t w0 = threadIdx.x; w0 < n; w0 += kFillBatch * step) {
+    const uint32_t* si = PL == kPlace4 ? tabs->si4 : tabs->si_packed;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t sub = lane >> 3;         // entry of the job
+    const uint32_t rep = (lane & 7u) * 4u;  // first of the lane's replicas
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nwaves = blockDim.x >> 6;
+    for (uint32_t j0 = wave; j0 < kJobs; j0 += kFillBatch * nwaves) {
         uint32_t v[kFillBatch];
 #pragma unroll
         for (uint32_t k = 0; k < kFillBatch; ++k) {
-            const uint32_t w = w0 + k * step;
-            uint32_t e;
-            if (PL == kPlace4)
-                e = (w >> 6) & 255u;
-            else if (PL == kPlace2)
-                e = (w >> 6) & 255u;
-            else
-                e = (w >> 5) & 255u;
-            v[k] = w < n ? src[e] : 0u;
+            const uint32_t job = j0 + k * nwaves;  // uniform
+            if (job < kTJobs)
+                v[k] = src[job * 8u + sub];
+            else if (job < kJobs)
+                v[k] = si[(job - kTJobs) * 8u + sub];
         }
 #pragma unroll
         for (uint32_t k = 0; k < kFillBatch; ++k) {
-            const uint32_t w = w0 + k * step;
-            uint32_t t;
-            if (PL == kPlace4)
-                t = (w >> 14) | (((w >> 5) & 1u) << 1);
-            else if (PL == kPlace2)
-                t = ((w >> 5) & 1u) << 1;
-            else
-                t = 0;
-            if (w < n)
-                lds[w] = t ? ((v[k] << (8 * t)) | (v[k] >> (32 - 8 * t))) : v[k];
-        }
-    }
-    if (kDecrypt) {
-        constexpr uint32_t ns = L::si_bytes / 4;
-        for (uint32_t w0 = threadIdx.x; w0 < ns; w0 += kFillBatch * step) {
-            uint32_t v[kFillBatch];
-#pragma unroll
-            for (uint32_t k = 0; k < kFillBatch; ++k) {
-                const uint32_t w = w0 + k * step;
-                if (PL == kPlace4)
-                    v[k] = w < ns ? tabs->si4[(w >> 5) & 255u] : 0u;
-                else
-                    v[k] = w < ns ? tabs->si_packed[(w >> 5) & 63u] : 0u;
-            }
-#pragma unroll
-            for (uint32_t k = 0; k < kFillBatch; ++k) {
-                const uint32_t w = w0 + k * step;
-                if (w < ns)
-                    lds[L::si_offset / 4 + w] = v[k];
+            const uint32_t job = j0 + k * nwaves;
+            if (job < kTJobs) {
+                const uint32_t w = (job * 8u + sub) * kStride + rep;
+                store4(lds, w, v[k]);                                      // T0
+                if (PL == kPlace4) {
+                    store4(lds, 16384u + w, (v[k] << 8) | (v[k] >> 24));   // T1
+                    store4(lds, 32u + w, (v[k] << 16) | (v[k] >> 16));     // T2
+                    store4(lds, 16416u + w, (v[k] << 24) | (v[k] >> 8));   // T3
+                } else if (PL == kPlace2) {
+                    store4(lds, 32u + w, (v[k] << 16) | (v[k] >> 16));     // T2
+                }
+            } else if (job < kJobs) {
+                store4(lds, L::si_offset / 4 + ((job - kTJobs) * 8u + sub) * 32u + rep, v[k]);
             }
         }
     }
@@ -254,15 +252,16 @@ __device__ __forceinline__ uint32_t packed_addr(uint32_t w, uint32_t m3, uint32_
     return and_or(shl16<5>(x), m1f80, and_or(x, m3, base));
 }
 
-// One block through all rounds. K(i) returns round-key word i (uniform).
-template <int NR, bool kDecrypt, int PL, class K>
-__device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
-                                             const K& key)
+// Inner rounds FIRST .. NR-1 and the final round of one block whose state
+// after round FIRST-1 is `in`.  K(i) returns round-key word i (uniform).
+template <int NR, bool kDecrypt, int PL, int FIRST, class K>
+__device__ __forceinline__ uint4 crypt_rounds(uint4 in, const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
+                                              const K& key)
 {
     constexpr int s = kDecrypt ? 3 : 1;  // neighbour column: j+1 (enc) or j-1 (dec), mod 4
-    uint32_t w[4] = {in.x ^ key(0), in.y ^ key(1), in.z ^ key(2), in.w ^ key(3)};
+    uint32_t w[4] = {in.x, in.y, in.z, in.w};
 #pragma unroll
-    for (int round = 1; round < NR; ++round) {
+    for (int round = FIRST; round < NR; ++round) {
         // v[j][t]: the lookup with byte t that output column j needs, issued
         // column by column, so column j can be combined once its four lookups
         // are back while the later columns' lookups are still in flight
@@ -348,6 +347,15 @@ __device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, cons
         }
     }
     return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// One block through all rounds: the first AddRoundKey, then rounds 1 .. NR.
+template <int NR, bool kDecrypt, int PL, class K>
+__device__ __forceinline__ uint4 crypt_block(uint4 in, const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
+                                             const K& key)
+{
+    return crypt_rounds<NR, kDecrypt, PL, 1>(
+        make_uint4(in.x ^ key(0), in.y ^ key(1), in.z ^ key(2), in.w ^ key(3)), lds, lb, key);
 }
 
 }  // namespace aesgpu

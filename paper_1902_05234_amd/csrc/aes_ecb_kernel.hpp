@@ -25,26 +25,27 @@ template <int NR, bool kDecrypt, int BPT, int PL>
 __global__ __launch_bounds__(1024) void ecb_kernel(const uint4* __restrict__ in, uint4* __restrict__ out,
                                                    uint64_t nblocks, RoundKeys rk)
 {
-    __shared__ uint32_t lds[Layout<PL, kDecrypt>::words];
-    fill_tables<PL, kDecrypt>(lds, &c_tables);
-    __syncthreads();
-    const LaneBases<PL, kDecrypt> lb(threadIdx.x);
-    auto key = [&](int i) { return rk.w[i]; };
-
+    __shared__ __align__(16) uint32_t lds[Layout<PL, kDecrypt>::words];
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t waves_per_grid = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t span = 64u * BPT;
     const uint64_t full_units = nblocks / span;  // units whose BPT blocks all exist
     uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     // Full units: the next unit's blocks are loaded before the current
-    // unit's rounds, so HBM latency hides behind them.  wv is uniform across
-    // the wave, so these branches are scalar and the loads unpredicated.
+    // unit's rounds, so HBM latency hides behind them; the first unit's
+    // blocks are requested before the table fill, so their round trip
+    // overlaps the fill's.  wv is uniform across the wave, so these branches
+    // are scalar and the loads unpredicated.
     uint4 cur[BPT];
     if (wv < full_units) {
 #pragma unroll
         for (int k = 0; k < BPT; ++k)
             cur[k] = in[wv * span + lane + 64u * k];
     }
+    fill_tables<PL, kDecrypt>(lds, &c_tables);
+    __syncthreads();
+    const LaneBases<PL, kDecrypt> lb(threadIdx.x);
+    auto key = [&](int i) { return rk.w[i]; };
     for (; wv < full_units; wv += waves_per_grid) {
         const uint64_t first = wv * span + lane;
         const uint64_t wn = wv + waves_per_grid;
