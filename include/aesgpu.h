@@ -285,8 +285,9 @@ int aes_batch_plan(const aes_msg *msgs, size_t nmsgs, uint32_t chunk_blocks, aes
 typedef struct {
     int32_t bpt;        /* 1, 2, 4 */
     int32_t wg;         /* multiple of 64 in [64, 1024] */
-    int32_t grid;       /* 0 = one workgroup per compute unit */
+    int32_t grid;       /* 0 = as many workgroups as fit on every compute unit at once */
     int32_t enc_groups; /* workgroups starting on the encryption list; <0 = by item share */
+    int32_t placement;  /* AES_PLACEMENT_TTABLE4 (0, the default), _TTABLE2 or _TTABLE1 */
 } aes_batch_config;
 
 /*
@@ -310,6 +311,14 @@ typedef struct {
 int aes_ecb_batch(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, const uint32_t *key_table_dev,
                   size_t n_slots, const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
                   uint32_t *counters_dev, const aes_batch_config *cfg, void *stream);
+
+/* Workgroups a launch of aes_ecb_batch with cfg (NULL: defaults) uses at most:
+ * cfg->grid if positive, else as many as fit on every compute unit at once
+ * (the occupancy of that bpt / placement / workgroup size).  A caller that
+ * splits the workgroups by bytes (enc_groups) sizes the split with it.
+ * AES_EINVAL for a config aes_ecb_batch refuses; AES_EHIP if the device
+ * cannot be queried. */
+int aes_batch_max_grid(const aes_batch_config *cfg, int *grid);
 
 /*
  * Serving: a native continuous-batching engine over aes_ecb_batch (not in the
@@ -354,10 +363,11 @@ typedef struct {
     uint32_t chunk_blocks;     /* work-item size, 1..AES_MAX_ITEM_BLOCKS */
     uint32_t max_batch_items;  /* work items per batch (sizes the workspace) */
     int32_t nslots;            /* batches in flight, 1..16 (one stream each) */
-    int32_t bpt, wg, grid;     /* batch kernel shape (grid 0 = one workgroup per CU) */
+    int32_t bpt, wg, grid;     /* batch kernel shape (grid 0 = as many workgroups as fit on every CU) */
     int32_t auto_release;      /* nonzero: output space is freed when a request completes */
     int32_t dry_run;           /* nonzero: no device work; batches complete after dry_run_seconds */
     double dry_run_seconds;
+    int32_t placement;         /* table placement of the batch kernel, as in aes_batch_config */
 } aes_serve_config;
 
 typedef struct {

@@ -42,7 +42,8 @@ class _Variant(ctypes.Structure):
 
 
 class _BatchConfig(ctypes.Structure):
-    _fields_ = [("bpt", ctypes.c_int32), ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("enc_groups", ctypes.c_int32)]
+    _fields_ = [("bpt", ctypes.c_int32), ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("enc_groups", ctypes.c_int32),
+                ("placement", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -102,6 +103,7 @@ def _lib() -> ctypes.CDLL:
                 "aes_batch_plan": ([_c_p, _c_sz, ctypes.c_uint32, _c_p, _c_sz, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_sz)], _c_i),
                 "aes_ecb_batch": ([_c_p, _c_sz, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
                                    ctypes.POINTER(_BatchConfig), _c_p], _c_i),
+                "aes_batch_max_grid": ([ctypes.POINTER(_BatchConfig), ctypes.POINTER(_c_i)], _c_i),
                 "aes_device_copy": ([_c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_roof_probe": ([_c_i, ctypes.c_uint32, _c_p, _c_sz, ctypes.POINTER(ctypes.c_uint64), _c_p], _c_i),
                 "aes_host_tables": ([_u8p, _u8p, _u32p, _u32p], _c_i),
@@ -125,7 +127,7 @@ def exported_symbols():
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
             "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
             "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
-            "aes_ecb_batch", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
+            "aes_ecb_batch", "aes_batch_max_grid", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
             "aes_pipe_destroy", "aes_pipe_run"]
@@ -366,6 +368,7 @@ class BatchConfig:
     wg: int = 1024
     grid: int = 0
     enc_groups: int = -1
+    placement: int = AES_PLACEMENT_TTABLE4
 
 
 def aes_ecb_batch(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out_base, counters_dev,
@@ -377,11 +380,20 @@ def aes_ecb_batch(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out
     if counters_dev.numel() * counters_dev.element_size() < 16:
         raise ValueError("counters need 4 uint32")
     c = cfg or BatchConfig()
-    bc = _BatchConfig(c.bpt, c.wg, c.grid, c.enc_groups)
+    bc = _BatchConfig(c.bpt, c.wg, c.grid, c.enc_groups, c.placement)
     _check(_lib().aes_ecb_batch(items_dev.data_ptr(), int(n_enc), int(n_dec), key_table_dev.data_ptr(), n_slots,
                                 in_base.data_ptr(), _blocks_of(in_base, "in_base"), out_base.data_ptr(),
                                 _blocks_of(out_base, "out_base"), counters_dev.data_ptr(), ctypes.byref(bc),
                                 _stream_handle(stream)))
+
+
+def aes_batch_max_grid(cfg: BatchConfig | None = None) -> int:
+    """Workgroups a batch launch with cfg uses at most (the persistent grid)."""
+    c = cfg or BatchConfig()
+    g = _c_i(0)
+    _check(_lib().aes_batch_max_grid(ctypes.byref(_BatchConfig(c.bpt, c.wg, c.grid, c.enc_groups, c.placement)),
+                                     ctypes.byref(g)))
+    return g.value
 
 
 def aes_device_copy(inp, out, nbytes: int | None = None, stream=None):
@@ -425,7 +437,7 @@ class _ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("chunk_blocks", ctypes.c_uint32),
                 ("max_batch_items", ctypes.c_uint32), ("nslots", ctypes.c_int32), ("bpt", ctypes.c_int32),
                 ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("auto_release", ctypes.c_int32),
-                ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double)]
+                ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double), ("placement", ctypes.c_int32)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -470,12 +482,14 @@ class Server:
 
     def __init__(self, key_table_dev=None, in_pool=None, out_arena=None, *, n_slots=None, in_blocks=None,
                  out_blocks=None, budget_bytes=32 << 30, chunk_blocks=2048, max_batch_items=1 << 18, nslots=4,
-                 bpt=4, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0):
+                 bpt=4, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0,
+                 placement=AES_PLACEMENT_TTABLE4):
         lib = _lib()
         _serve_sigs(lib)
         self._lib = lib
         self.cfg = _ServeConfig(int(budget_bytes), int(chunk_blocks), int(max_batch_items), int(nslots), int(bpt),
-                                int(wg), int(grid), int(bool(auto_release)), int(bool(dry_run)), float(dry_run_seconds))
+                                int(wg), int(grid), int(bool(auto_release)), int(bool(dry_run)), float(dry_run_seconds),
+                                int(placement))
         ws = lib.aes_server_workspace_bytes(ctypes.byref(self.cfg))
         st = lib.aes_server_staging_bytes(ctypes.byref(self.cfg))
         self._keep = [key_table_dev, in_pool, out_arena]

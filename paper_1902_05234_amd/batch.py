@@ -90,10 +90,7 @@ def prepare(msgs: np.ndarray, key_table_dev, in_arena, out_arena, chunk_blocks: 
 
 
 def _grid(c: aes.BatchConfig) -> int:
-    if c.grid > 0:
-        return c.grid
-    import torch
-    return torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    return aes.aes_batch_max_grid(c)
 
 
 def messages_from_mix(mix, key_slots=None) -> np.ndarray:

@@ -270,10 +270,38 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     return AES_OK;
 }
 
+// Workgroups of a batch launch at most: cfg.grid, or as many as fit on every
+// CU at once for the configured variant.
+int batch_max_grid(const aes_batch_config& c, int* out)
+{
+    if (c.bpt != 1 && c.bpt != 2 && c.bpt != 4)
+        return fail(AES_EINVAL, "bpt must be 1, 2 or 4, got %d", c.bpt);
+    if (c.wg < 64 || c.wg > 1024 || c.wg % 64)
+        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", c.wg);
+    if (c.placement != AES_PLACEMENT_TTABLE4 && c.placement != AES_PLACEMENT_TTABLE2 &&
+        c.placement != AES_PLACEMENT_TTABLE1)
+        return fail(AES_EINVAL, "the batch kernel takes the table placements 0, 1 or 2, got %d", c.placement);
+    if (c.grid < 0)
+        return fail(AES_EINVAL, "grid must be >= 0 (0 = as many workgroups as fit at once), got %d", c.grid);
+    if (c.grid > 0) {
+        *out = c.grid;
+        return AES_OK;
+    }
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    int per_cu = 0;
+    hipError_t e = batch_groups_per_cu(c.bpt, c.placement, c.wg, &per_cu);
+    if (e != hipSuccess)
+        return fail_hip(e, "batch kernel occupancy query");
+    *out = cus * per_cu;
+    return AES_OK;
+}
+
 // Arguments of one batch launch, checked; the caller supplies the counters.
 struct BatchLaunch {
     BatchArgs args;
-    int bpt, wg, grid;
+    int bpt, wg, grid, placement;
 };
 
 int check_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, const uint32_t* key_table_dev,
@@ -295,26 +323,23 @@ int check_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, cons
     const uintptr_t ib = reinterpret_cast<uintptr_t>(in_base), ob = reinterpret_cast<uintptr_t>(out_base);
     if (ib != ob && ib < ob + (uint64_t)out_blocks * 16u && ob < ib + (uint64_t)in_blocks * 16u)
         return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
-    aes_batch_config c{1, 1024, 0, -1};
+    aes_batch_config c{1, 1024, 0, -1, AES_PLACEMENT_TTABLE4};
     if (cfg)
         c = *cfg;
-    if (c.bpt != 1 && c.bpt != 2 && c.bpt != 4)
-        return fail(AES_EINVAL, "bpt must be 1, 2 or 4, got %d", c.bpt);
-    if (c.wg < 64 || c.wg > 1024 || c.wg % 64)
-        return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", c.wg);
-    int cus = device_cu_count();
-    if (cus <= 0)
-        return fail(AES_EHIP, "cannot query the current HIP device");
+    int max_grid = 0;
+    int rc = batch_max_grid(c, &max_grid);
+    if (rc != AES_OK)
+        return rc;
     int grid = 0, enc_groups = 0;
     // the item counts stand in for the byte shares (the items live on the device)
-    batch_grid(n_enc, n_dec, n_enc, n_enc + n_dec, c.wg, c.grid > 0 ? c.grid : cus, c.enc_groups, &grid,
-               &enc_groups);
+    batch_grid(n_enc, n_dec, n_enc, n_enc + n_dec, c.wg, max_grid, c.enc_groups, &grid, &enc_groups);
     out->args = BatchArgs{reinterpret_cast<const WorkItem*>(items_dev), (uint32_t)n_enc, (uint32_t)n_dec,
                           key_table_dev, (uint32_t)n_slots, in_base, out_base, (uint64_t)in_blocks,
                           (uint64_t)out_blocks, nullptr, (uint32_t)enc_groups};
     out->bpt = c.bpt;
     out->wg = c.wg;
     out->grid = grid;
+    out->placement = c.placement;
     return AES_OK;
 }
 
@@ -553,10 +578,20 @@ int aes_ecb_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, co
     if (rc != AES_OK)
         return rc;
     b.args.counters = counters_dev;
-    hipError_t e = launch_batch(b.args, b.bpt, b.grid, b.wg, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_batch(b.args, b.bpt, b.placement, b.grid, b.wg, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "batch kernel launch");
     return AES_OK;
+}
+
+int aes_batch_max_grid(const aes_batch_config* cfg, int* grid)
+{
+    if (grid == nullptr)
+        return fail(AES_EINVAL, "null grid pointer");
+    aes_batch_config c{1, 1024, 0, -1, AES_PLACEMENT_TTABLE4};
+    if (cfg)
+        c = *cfg;
+    return batch_max_grid(c, grid);
 }
 
 int aes_host_tables(uint8_t* sbox, uint8_t* inv_sbox, uint32_t* te0, uint32_t* td0)

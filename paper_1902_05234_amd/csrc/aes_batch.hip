@@ -6,18 +6,23 @@
 // that item's round keys as uniform values, and runs the same round core as
 // the plain kernel for the item's key size.
 //
-// LDS holds the tables of one direction only (128 KiB + 32 KiB), so the
-// workgroups are split by role: the first `enc_groups` start on the
-// encryption list, the others on the decryption list; when a list runs dry a
-// workgroup reloads LDS with the other direction's tables and helps drain the
-// other list.  The last workgroup to finish resets the claim counters, so a
-// captured graph can replay the launch with no separate reset node.
+// LDS holds the tables of one direction only (4 tables: 128 KiB + 32 KiB of
+// InvS; 2 tables: 64 + 8 KiB; 1 table: 32 + 8 KiB), so the workgroups are
+// split by role: the first `enc_groups` start on the encryption list, the
+// others on the decryption list; when a list runs dry a workgroup reloads
+// LDS with the other direction's tables and helps drain the other list.  The
+// last workgroup to finish resets the claim counters, so a captured graph can
+// replay the launch with no separate reset node.  The table placement and the
+// workgroup size are the same design axes as in the plain kernel (section
+// 4.2 keeps the tables in shared memory; the placements trade LDS size, and
+// so resident waves, against VALU work).
 //
 // Every item is checked against the arena sizes, the key-table size and the
 // largest item size before use; a bad item is skipped and counted in
 // counters[3].
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "aes_device.hpp"
@@ -28,15 +33,20 @@ namespace aesgpu {
 constexpr int kSlotWords = 128;  // rk_enc at 0, rk_dec at 64, Nr at 124
 constexpr int kSlotNr = 124;
 
-template <int NR, bool kDecrypt, int BPT>
+template <int NR, bool kDecrypt, int BPT, int PL>
 __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __restrict__ out, uint32_t nblocks,
-                                         const uint32_t* lds, const LaneBases<kPlace4, kDecrypt>& lb,
+                                         const uint32_t* lds, const LaneBases<PL, kDecrypt>& lb,
                                          const uint32_t* __restrict__ kp)
 {
     uint32_t k[4 * (NR + 1)];
 #pragma unroll
-    for (int i = 0; i < 4 * (NR + 1); ++i)
+    for (int i = 0; i < 4 * (NR + 1); ++i) {
         k[i] = __builtin_amdgcn_readfirstlane(kp[i]);
+        // the 2-table round takes inner-round key words turned right by 8
+        // bits (see crypt_rounds); uniform values, so scalar work
+        if (PL == kPlace2 && i >= 4 && i < 4 * NR)
+            k[i] = (k[i] >> 8) | (k[i] << 24);
+    }
     auto key = [&](int i) { return k[i]; };
     const uint32_t lane = threadIdx.x & 63u;
     // Whole units first, then the ragged one: every index stays below
@@ -51,7 +61,7 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
             x[j] = in[first + 64u * j];
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
-            x[j] = crypt_block<NR, kDecrypt, kPlace4>(x[j], lds, lb, key);
+            x[j] = crypt_block<NR, kDecrypt, PL>(x[j], lds, lb, key);
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
             out[first + 64u * j] = x[j];
@@ -62,12 +72,12 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
         for (int j = 0; j < BPT; ++j) {
             const uint32_t b = b0 + lane + 64u * j;
             if (b < nblocks)
-                out[b] = crypt_block<NR, kDecrypt, kPlace4>(in[b], lds, lb, key);
+                out[b] = crypt_block<NR, kDecrypt, PL>(in[b], lds, lb, key);
         }
     }
 }
 
-template <bool kDecrypt, int BPT>
+template <bool kDecrypt, int BPT, int PL>
 __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32_t first_item, uint32_t n_items,
                                       const uint32_t* __restrict__ key_table, uint32_t n_slots,
                                       const uint4* __restrict__ in_base, uint4* __restrict__ out_base,
@@ -75,7 +85,7 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
                                       const uint32_t* lds)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const LaneBases<kPlace4, kDecrypt> lb(threadIdx.x);
+    const LaneBases<PL, kDecrypt> lb(threadIdx.x);
     for (;;) {
         uint32_t idx = 0;
         if (lane == 0)
@@ -96,9 +106,9 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
         const int nr = ok ? (int)__builtin_amdgcn_readfirstlane(kp[kSlotNr]) : 0;
         const uint32_t* kd = kp + (kDecrypt ? 64 : 0);
         switch (nr) {
-        case 10: run_item<10, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
-        case 12: run_item<12, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
-        case 14: run_item<14, kDecrypt, BPT>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        case 10: run_item<10, kDecrypt, BPT, PL>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        case 12: run_item<12, kDecrypt, BPT, PL>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
+        case 14: run_item<14, kDecrypt, BPT, PL>(in_base + in_b, out_base + out_b, nb, lds, lb, kd); break;
         default:
             if (lane == 0)
                 atomicAdd(&counters[3], 1u);
@@ -107,28 +117,30 @@ __device__ __forceinline__ void drain(const WorkItem* __restrict__ items, uint32
     }
 }
 
-template <int BPT>
-__global__ __launch_bounds__(1024) void batch_kernel(const WorkItem* __restrict__ items, uint32_t n_enc,
+// The 2- and 1-table kernels are built for 8 waves per SIMD (at most 64
+// VGPRs), so two 1024-thread workgroups share a CU, as in the plain kernel.
+template <int BPT, int PL>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PL == kPlace4 ? 4 : 8))) void batch_kernel(const WorkItem* __restrict__ items, uint32_t n_enc,
                                                      uint32_t n_dec, const uint32_t* __restrict__ key_table,
                                                      uint32_t n_slots, const uint4* __restrict__ in_base,
                                                      uint4* __restrict__ out_base, uint64_t in_blocks,
                                                      uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups)
 {
-    __shared__ __align__(16) uint32_t lds[Layout<kPlace4, true>::words];
+    __shared__ __align__(16) uint32_t lds[Layout<PL, true>::words];  // the larger of the two directions
     bool dec = blockIdx.x >= enc_groups;
     for (int pass = 0; pass < 2; ++pass, dec = !dec) {
         if ((dec ? n_dec : n_enc) == 0)
             continue;  // uniform across the grid: no tables to load, no barrier to meet
         if (dec)
-            fill_tables<kPlace4, true>(lds, &c_tables);
+            fill_tables<PL, true>(lds, &c_tables);
         else
-            fill_tables<kPlace4, false>(lds, &c_tables);
+            fill_tables<PL, false>(lds, &c_tables);
         __syncthreads();
         if (dec)
-            drain<true, BPT>(items, n_enc, n_dec, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
+            drain<true, BPT, PL>(items, n_enc, n_dec, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
                              counters, lds);
         else
-            drain<false, BPT>(items, 0, n_enc, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
+            drain<false, BPT, PL>(items, 0, n_enc, key_table, n_slots, in_base, out_base, in_blocks, out_blocks,
                               counters, lds);
         __syncthreads();  // every wave is done with these tables before LDS is refilled
     }
@@ -170,18 +182,76 @@ void batch_grid(uint64_t n_enc, uint64_t n_dec, uint64_t enc_blocks, uint64_t to
     *enc_groups = (int)e;
 }
 
-hipError_t launch_batch(const BatchArgs& a, int bpt, int grid, int wg, hipStream_t stream)
+namespace {
+
+template <int PL>
+const void* batch_kernel_bpt(int bpt)
 {
-#define AESGPU_BATCH_LAUNCH(B)                                                                                  \
-    hipLaunchKernelGGL(batch_kernel<B>, dim3(grid), dim3(wg), 0, stream, a.items, a.n_enc, a.n_dec, a.key_table, \
-                       a.n_slots, static_cast<const uint4*>(a.in_base), static_cast<uint4*>(a.out_base),        \
-                       a.in_blocks, a.out_blocks, a.counters, a.enc_groups)
     switch (bpt) {
-    case 1: AESGPU_BATCH_LAUNCH(1); break;
-    case 2: AESGPU_BATCH_LAUNCH(2); break;
-    case 4: AESGPU_BATCH_LAUNCH(4); break;
+    case 1: return reinterpret_cast<const void*>(batch_kernel<1, PL>);
+    case 2: return reinterpret_cast<const void*>(batch_kernel<2, PL>);
+    case 4: return reinterpret_cast<const void*>(batch_kernel<4, PL>);
+    default: return nullptr;
+    }
+}
+
+const void* batch_kernel_for(int bpt, int placement)
+{
+    switch (placement) {
+    case kPlace4: return batch_kernel_bpt<kPlace4>(bpt);
+    case kPlace2: return batch_kernel_bpt<kPlace2>(bpt);
+    case kPlace1: return batch_kernel_bpt<kPlace1>(bpt);
+    default: return nullptr;
+    }
+}
+
+// Workgroups per CU of each (bpt, placement, workgroup size), from the
+// occupancy query on first use; 0 = not asked yet.
+std::atomic<int> g_groups_per_cu[3][3][16];
+
+int bpt_index(int bpt) { return bpt == 1 ? 0 : bpt == 2 ? 1 : bpt == 4 ? 2 : -1; }
+
+}  // namespace
+
+hipError_t batch_groups_per_cu(int bpt, int placement, int wg, int* per_cu)
+{
+    const void* k = batch_kernel_for(bpt, placement);
+    const int bi = bpt_index(bpt);
+    if (k == nullptr || bi < 0 || wg < 64 || wg > 1024 || wg % 64)
+        return hipErrorInvalidValue;
+    std::atomic<int>& slot = g_groups_per_cu[bi][placement][wg / 64 - 1];
+    int n = slot.load(std::memory_order_relaxed);
+    if (n <= 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, wg, 0);
+        if (e != hipSuccess)
+            return e;
+        n = n > 0 ? n : 1;
+        slot.store(n, std::memory_order_relaxed);
+    }
+    *per_cu = n;
+    return hipSuccess;
+}
+
+hipError_t launch_batch(const BatchArgs& a, int bpt, int placement, int grid, int wg, hipStream_t stream)
+{
+#define AESGPU_BATCH_LAUNCH(B, P)                                                                                  \
+    hipLaunchKernelGGL((batch_kernel<B, P>), dim3(grid), dim3(wg), 0, stream, a.items, a.n_enc, a.n_dec,           \
+                       a.key_table, a.n_slots, static_cast<const uint4*>(a.in_base), static_cast<uint4*>(a.out_base), \
+                       a.in_blocks, a.out_blocks, a.counters, a.enc_groups)
+#define AESGPU_BATCH_PLACEMENT(P)                   \
+    switch (bpt) {                                  \
+    case 1: AESGPU_BATCH_LAUNCH(1, P); break;       \
+    case 2: AESGPU_BATCH_LAUNCH(2, P); break;       \
+    case 4: AESGPU_BATCH_LAUNCH(4, P); break;       \
+    default: return hipErrorInvalidValue;           \
+    }
+    switch (placement) {
+    case kPlace4: AESGPU_BATCH_PLACEMENT(kPlace4); break;
+    case kPlace2: AESGPU_BATCH_PLACEMENT(kPlace2); break;
+    case kPlace1: AESGPU_BATCH_PLACEMENT(kPlace1); break;
     default: return hipErrorInvalidValue;
     }
+#undef AESGPU_BATCH_PLACEMENT
 #undef AESGPU_BATCH_LAUNCH
     return hipGetLastError();
 }

@@ -87,7 +87,12 @@ struct BatchArgs {
     uint32_t enc_groups;   // workgroups that start on the encryption list
 };
 
-hipError_t launch_batch(const BatchArgs& args, int bpt, int grid, int wg, hipStream_t stream);
+// placement: kPlace4 / kPlace2 / kPlace1 (the table placements of the plain kernel)
+hipError_t launch_batch(const BatchArgs& args, int bpt, int placement, int grid, int wg, hipStream_t stream);
+
+// Workgroups of the batch kernel variant (bpt, placement, wg) that fit on one
+// CU at once (LDS and registers); cached per variant after the first query.
+hipError_t batch_groups_per_cu(int bpt, int placement, int wg, int* per_cu);
 
 // Grid of a batch launch: at most max_grid workgroups, no more than the
 // items can keep busy, at least one per non-empty direction; enc_groups is

@@ -112,6 +112,7 @@ struct aes_server {
     aes_serve_config cfg{};
     int device = 0;
     int cus = 0;
+    int max_grid = 0;  // workgroups per batch launch at most (cfg.grid, or all that fit at once)
     const uint32_t* key_table = nullptr;
     size_t n_slots = 0;
     const void* in_pool = nullptr;
@@ -221,13 +222,12 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
                                            hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) {
         int grid = 0, enc_groups = 0;
-        batch_grid(ne, nd, enc_b, tot_b, s->cfg.wg, s->cfg.grid > 0 ? s->cfg.grid : s->cus, -1, &grid,
-                   &enc_groups);
+        batch_grid(ne, nd, enc_b, tot_b, s->cfg.wg, s->max_grid, -1, &grid, &enc_groups);
         const void* items = direct ? static_cast<const void*>(sl.staging) : static_cast<const void*>(sl.items_dev);
         BatchArgs a{static_cast<const WorkItem*>(items), (uint32_t)ne, (uint32_t)nd, s->key_table,
                     (uint32_t)s->n_slots, s->in_pool, s->out_arena, (uint64_t)s->in_blocks, (uint64_t)s->out_blocks,
                     sl.counters_dev, (uint32_t)enc_groups};
-        e = launch_batch(a, s->cfg.bpt, grid, s->cfg.wg, sl.stream);
+        e = launch_batch(a, s->cfg.bpt, s->cfg.placement, grid, s->cfg.wg, sl.stream);
     }
     if (e == hipSuccess)
         e = hipEventRecord(sl.event, sl.stream);
@@ -405,9 +405,12 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
     const aes_serve_config& c = *cfg;
     if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.chunk_blocks > AES_MAX_ITEM_BLOCKS ||
         c.max_batch_items == 0 || c.budget_bytes == 0 || (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 ||
-        c.wg > 1024 || c.wg % 64)
+        c.wg > 1024 || c.wg % 64 || c.grid < 0 ||
+        (c.placement != AES_PLACEMENT_TTABLE4 && c.placement != AES_PLACEMENT_TTABLE2 &&
+         c.placement != AES_PLACEMENT_TTABLE1))
         return fail(AES_EINVAL, "serve config out of range (nslots 1..16, chunk 1..AES_MAX_ITEM_BLOCKS, "
-                                "items/budget > 0, bpt 1/2/4, wg multiple of 64 in [64, 1024])");
+                                "items/budget > 0, bpt 1/2/4, wg multiple of 64 in [64, 1024], grid >= 0, "
+                                "placement 0/1/2)");
     if (!c.dry_run && (key_table_dev == nullptr || in_pool == nullptr || out_arena == nullptr ||
                        workspace_dev == nullptr || staging_host == nullptr))
         return fail(AES_EINVAL, "null key table, input pool, output arena, workspace or staging");
@@ -440,6 +443,10 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
         s->cus = device_cu_count();
         if (s->cus <= 0)
             rc = AES_EHIP;
+        int per_cu = 0;
+        if (rc == AES_OK && c.grid == 0 && batch_groups_per_cu(c.bpt, c.placement, c.wg, &per_cu) != hipSuccess)
+            rc = AES_EHIP;
+        s->max_grid = c.grid > 0 ? c.grid : s->cus * per_cu;
     }
     for (int i = 0; i < c.nslots && rc == AES_OK; ++i) {
         Slot& sl = s->slots[i];

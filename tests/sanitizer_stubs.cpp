@@ -37,7 +37,9 @@ hipError_t launch_cbc_decrypt(const LaunchShape&, int, int, const void*, void*, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(const BatchArgs&, int, int, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_batch(const BatchArgs&, int, int, int, int, hipStream_t) { return hipErrorInvalidValue; }
+
+hipError_t batch_groups_per_cu(int, int, int, int*) { return hipErrorInvalidValue; }
 
 void batch_grid(uint64_t, uint64_t, uint64_t, uint64_t, int, int max_grid, int, int* grid, int* enc_groups)
 {

@@ -47,6 +47,32 @@ def test_mixed_batch_matches_oracle(oracle_lib, chunk, bpt):
     assert not b.counters_dev[:3].any(), "claim counters must be reset by the last workgroup"
 
 
+@pytest.mark.parametrize("placement", [aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2,
+                                       aes.AES_PLACEMENT_TTABLE1])
+@pytest.mark.parametrize("wg,bpt", [(256, 1), (512, 2), (1024, 4), (1024, 1)])
+def test_every_batch_variant_matches_oracle(oracle_lib, placement, wg, bpt):
+    """Each table placement and workgroup size of the batch kernel (the
+    autotuner's axes) gives the oracle's output on a mixed batch, with items
+    of a ragged size (100 blocks) and a grid small enough that workgroups
+    switch direction."""
+    torch = cuda()
+    cfg = aes.BatchConfig(bpt=bpt, wg=wg, placement=placement, grid=5)
+    mix, keys, x, b = build(31 + placement * 7 + wg + bpt, 200, 128 << 10, 100, cfg)
+    b.launch()
+    torch.cuda.synchronize()
+    assert b.rejected_items() == 0
+    check_against_oracle(oracle_lib, mix, keys, x, b.out_arena.cpu().numpy())
+    assert not b.counters_dev[:3].any(), "claim counters must be reset by the last workgroup"
+    # a second launch (persistent grid, as the library sizes it) gives the same output
+    first = b.out_arena.clone()
+    b2 = batch.prepare(b.msgs, b.key_table_dev, b.in_arena, b.out_arena, chunk_blocks=100,
+                       cfg=aes.BatchConfig(bpt=bpt, wg=wg, placement=placement))
+    b.out_arena.zero_()
+    b2.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(b.out_arena, first)
+
+
 def test_batch_equals_plain_kernel_per_message():
     torch = cuda()
     mix, keys, x, b = build(21, 500, 1 << 20, 1024)
