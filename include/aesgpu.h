@@ -312,6 +312,29 @@ int aes_ecb_batch(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, co
                   size_t n_slots, const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
                   uint32_t *counters_dev, const aes_batch_config *cfg, void *stream);
 
+/*
+ * aes_ecb_batch_noalloc -- aes_ecb_batch for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the same launch, with the four claim counters in a
+ * scratch array of AES_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device (a static device array, kept until the process ends) instead of a
+ * caller's counters_dev.  The caller still passes the work list, key table
+ * and arenas, with the meaning, checks and errors of aes_ecb_batch.  The call
+ * allocates nothing: it enqueues a one-workgroup kernel that zeroes the
+ * counters, then the batch kernel, both on `stream` (so a captured graph
+ * holds two kernel nodes and no memset).  A launch needs 16 bytes of the
+ * scratch whatever its sizes, so no size exceeds it.  Rejected items are
+ * skipped as in aes_ecb_batch but their count is not reported.  Every call on
+ * one device shares that device's scratch: calls whose launches overlap in
+ * time on one device (different streams, or graphs replayed concurrently)
+ * race on the counters and must not be issued.  AES_EHIP if the scratch's
+ * device address cannot be obtained or a launch fails.
+ */
+#define AES_NOALLOC_SCRATCH_BYTES 256
+int aes_ecb_batch_noalloc(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, const uint32_t *key_table_dev,
+                          size_t n_slots, const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
+                          const aes_batch_config *cfg, void *stream);
+
 /* Workgroups a launch of aes_ecb_batch with cfg (NULL: defaults) uses at most:
  * cfg->grid if positive, else as many as fit on every compute unit at once
  * (the occupancy of that bpt / placement / workgroup size).  A caller that

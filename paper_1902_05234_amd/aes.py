@@ -104,6 +104,8 @@ def _lib() -> ctypes.CDLL:
                 "aes_ecb_batch": ([_c_p, _c_sz, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
                                    ctypes.POINTER(_BatchConfig), _c_p], _c_i),
                 "aes_batch_max_grid": ([ctypes.POINTER(_BatchConfig), ctypes.POINTER(_c_i)], _c_i),
+                "aes_ecb_batch_noalloc": ([_c_p, _c_sz, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz,
+                                           ctypes.POINTER(_BatchConfig), _c_p], _c_i),
                 "aes_device_copy": ([_c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_roof_probe": ([_c_i, ctypes.c_uint32, _c_p, _c_sz, ctypes.POINTER(ctypes.c_uint64), _c_p], _c_i),
                 "aes_host_tables": ([_u8p, _u8p, _u32p, _u32p], _c_i),
@@ -127,7 +129,7 @@ def exported_symbols():
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
             "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
             "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
-            "aes_ecb_batch", "aes_batch_max_grid", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
+            "aes_ecb_batch", "aes_ecb_batch_noalloc", "aes_batch_max_grid", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
             "aes_pipe_destroy", "aes_pipe_run"]
@@ -385,6 +387,21 @@ def aes_ecb_batch(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out
                                 in_base.data_ptr(), _blocks_of(in_base, "in_base"), out_base.data_ptr(),
                                 _blocks_of(out_base, "out_base"), counters_dev.data_ptr(), ctypes.byref(bc),
                                 _stream_handle(stream)))
+
+
+def aes_ecb_batch_noalloc(items_dev, n_enc: int, n_dec: int, key_table_dev, in_base, out_base,
+                          cfg: BatchConfig | None = None, stream=None):
+    """aes_ecb_batch with the claim counters in the library's per-device
+    scratch (no counters argument; the call allocates nothing)."""
+    n_slots = (key_table_dev.numel() * key_table_dev.element_size()) // (4 * AES_KEY_SLOT_WORDS)
+    if items_dev.numel() * items_dev.element_size() < (n_enc + n_dec) * ITEM_DTYPE.itemsize:
+        raise ValueError("work list tensor smaller than n_enc + n_dec items")
+    c = cfg or BatchConfig()
+    bc = _BatchConfig(c.bpt, c.wg, c.grid, c.enc_groups, c.placement)
+    _check(_lib().aes_ecb_batch_noalloc(items_dev.data_ptr(), int(n_enc), int(n_dec), key_table_dev.data_ptr(),
+                                        n_slots, in_base.data_ptr(), _blocks_of(in_base, "in_base"),
+                                        out_base.data_ptr(), _blocks_of(out_base, "out_base"), ctypes.byref(bc),
+                                        _stream_handle(stream)))
 
 
 def aes_batch_max_grid(cfg: BatchConfig | None = None) -> int:

@@ -584,6 +584,23 @@ int aes_ecb_batch(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, co
     return AES_OK;
 }
 
+int aes_ecb_batch_noalloc(const aes_work_item* items_dev, size_t n_enc, size_t n_dec, const uint32_t* key_table_dev,
+                          size_t n_slots, const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks,
+                          const aes_batch_config* cfg, void* stream)
+{
+    if (n_enc + n_dec == 0)
+        return AES_OK;
+    BatchLaunch b;
+    int rc = check_batch(items_dev, n_enc, n_dec, key_table_dev, n_slots, in_base, in_blocks, out_base, out_blocks,
+                         cfg, &b);
+    if (rc != AES_OK)
+        return rc;
+    hipError_t e = launch_batch_noalloc(b.args, b.bpt, b.placement, b.grid, b.wg, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "batch kernel launch (no-allocation form)");
+    return AES_OK;
+}
+
 int aes_batch_max_grid(const aes_batch_config* cfg, int* grid)
 {
     if (grid == nullptr)

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 
 #include "aes_device.hpp"
 #include "aes_internal.hpp"
@@ -254,6 +255,70 @@ hipError_t launch_batch(const BatchArgs& a, int bpt, int placement, int grid, in
 #undef AESGPU_BATCH_PLACEMENT
 #undef AESGPU_BATCH_LAUNCH
     return hipGetLastError();
+}
+
+// Claim counters of the allocation-free batched launch
+// (aes_ecb_batch_noalloc).  One copy per device, held until the process
+// ends; kScratchWords words, of which a launch uses the first four, laid out
+// as the counters of aes_ecb_batch.  Host code never passes this array's
+// name to a kernel: it takes the device address from hipGetSymbolAddress,
+// once per device, with that device current.
+constexpr uint32_t kScratchWords = AES_NOALLOC_SCRATCH_BYTES / 4;
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::atomic<uint32_t*> g_scratch[64];  // device address of `scratch`, per device
+
+// Zero n words with one small kernel (a kernel node, not a memset node, when
+// a caller captures the launch in a graph).
+__global__ __launch_bounds__(64) void zero_words(uint32_t* p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace
+
+hipError_t noalloc_scratch(uint32_t** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    uint32_t* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch[dev].load(std::memory_order_relaxed);
+        if (p == nullptr) {
+            void* addr = nullptr;
+            e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess)
+                return e;
+            p = static_cast<uint32_t*>(addr);
+            g_scratch[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+hipError_t launch_batch_noalloc(BatchArgs a, int bpt, int placement, int grid, int wg, hipStream_t stream)
+{
+    uint32_t* p = nullptr;
+    hipError_t e = noalloc_scratch(&p);
+    if (e != hipSuccess)
+        return e;
+    // the counters start at zero whatever an earlier launch left
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, p, 4u);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    a.counters = p;
+    return launch_batch(a, bpt, placement, grid, wg, stream);
 }
 
 }  // namespace aesgpu

@@ -90,6 +90,14 @@ struct BatchArgs {
 // placement: kPlace4 / kPlace2 / kPlace1 (the table placements of the plain kernel)
 hipError_t launch_batch(const BatchArgs& args, int bpt, int placement, int grid, int wg, hipStream_t stream);
 
+// launch_batch with the claim counters in the library's per-device scratch
+// array (args.counters is ignored), zeroed by a kernel on `stream` first.
+hipError_t launch_batch_noalloc(BatchArgs args, int bpt, int placement, int grid, int wg, hipStream_t stream);
+
+// Device address of the per-device scratch array (hipGetSymbolAddress on the
+// current device's first call).
+hipError_t noalloc_scratch(uint32_t** out);
+
 // Workgroups of the batch kernel variant (bpt, placement, wg) that fit on one
 // CU at once (LDS and registers); cached per variant after the first query.
 hipError_t batch_groups_per_cu(int bpt, int placement, int wg, int* per_cu);

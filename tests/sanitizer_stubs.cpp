@@ -41,6 +41,8 @@ hipError_t launch_batch(const BatchArgs&, int, int, int, int, hipStream_t) { ret
 
 hipError_t batch_groups_per_cu(int, int, int, int*) { return hipErrorInvalidValue; }
 
+hipError_t launch_batch_noalloc(BatchArgs, int, int, int, int, hipStream_t) { return hipErrorInvalidValue; }
+
 void batch_grid(uint64_t, uint64_t, uint64_t, uint64_t, int, int max_grid, int, int* grid, int* enc_groups)
 {
     *grid = max_grid;
