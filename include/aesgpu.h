@@ -87,8 +87,15 @@ int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_
 #define AES_PLACEMENT_BITSLICED 3 /* no tables: 32 blocks per lane as 128 bit slices, the S-box as a
                                      Boolean circuit; ECB only, bpt is ignored (512 bytes per thread),
                                      wg at most 256 */
+/* One column word per lane (4 bytes per thread): the four lanes of a quad
+ * hold the four columns of one block and exchange them each round, so a
+ * lane issues four lookups per round instead of sixteen.  For launches bound
+ * by the latency of one block's rounds (small buffers). */
+#define AES_BPT_COLUMN 0
 typedef struct {
-    int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes) */
+    int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes), or
+                          AES_BPT_COLUMN: a quarter block, four lanes per block (ECB, table
+                          placements only) */
     int32_t wg;        /* workgroup size: multiple of 64 in [64, 1024] */
     int32_t placement; /* AES_PLACEMENT_* */
     int32_t grid;      /* workgroups; 0 = persistent (compute units x workgroups that fit on one) */

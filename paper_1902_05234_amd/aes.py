@@ -18,9 +18,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # another build of the library (say, one with host sanitizers) can be named in AESGPU_LIBRARY
 LIBRARY = os.environ.get("AESGPU_LIBRARY") or os.path.join(HERE, "libaesgpu.so")
 TUNE_FILE_ENV = "AESGPU_TUNE_FILE"  # path of an autotune record to install when the library loads
+TUNE_FORCE_ENV = "AESGPU_TUNE_FORCE"  # "1": install that record even if made on another device or sources
 
 AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0, -1, -2, -3, -4, -5, -6
 AES_PLACEMENT_TTABLE4, AES_PLACEMENT_TTABLE2, AES_PLACEMENT_TTABLE1, AES_PLACEMENT_BITSLICED = 0, 1, 2, 3
+AES_BPT_COLUMN = 0  # Variant.bpt: one column word per lane, four lanes per block
 AES_KEY_SLOT_WORDS, AES_KEY_SLOT_ENC, AES_KEY_SLOT_DEC, AES_KEY_SLOT_NR = 128, 0, 64, 124
 AES_SIZE_BUCKETS = 6
 
@@ -118,9 +120,11 @@ def _lib() -> ctypes.CDLL:
             path = os.environ.get(TUNE_FILE_ENV)
             if path:
                 # an autotune record (paper_1902_05234_amd.autotune --out) replaces the
-                # compiled-in defaults for every size it covers
+                # compiled-in defaults for every size it covers; a record made on
+                # another device or for other kernel sources is refused unless
+                # AESGPU_TUNE_FORCE=1
                 from . import autotune
-                autotune.apply(autotune.load(path))
+                autotune.apply(autotune.load(path), force=os.environ.get(TUNE_FORCE_ENV) == "1")
     return _lib_obj
 
 

@@ -8,13 +8,25 @@ before it is timed.  Each (key size, direction, size bucket) is timed at two or
 three sizes spread over the bucket: the best variant for a bucket changes
 inside it (a buffer of a few wave units leaves waves idle with 64 bytes per
 thread but not with 16), so the winner is the variant whose worst ratio to
-the fastest variant over those sizes is highest.  The record is JSON keyed
-by device and library source hash and can be installed into the library's
-tuning table with ``apply``.
+the fastest variant over those sizes is highest.  Launches up to 64 MiB are
+timed inside replayed HIP graphs (the host's per-call cost stays out); the
+largest bucket is timed the way the library runs it there, with sustained
+back-to-back launches: every variant is screened with short interleaved
+timings, and the best few are then timed again over seconds of back-to-back
+load in interleaved passes, where the engine clock has settled.
 
-Batched path: chunk size (blocks per work item) x blocks per thread.
+Batched path: chunk size (blocks per work item) x blocks per thread x
+workgroup size x table placement, on the 20,000-message mix.
+
+The record is JSON keyed by device (name and architecture) and by the hash
+of the library's device sources.  ``apply`` installs its plain-path winners
+into the library's tuning table and refuses a record made on another device
+or for other kernel sources unless forced.  ``emit_defaults`` turns a record
+into the compiled-in default table (``csrc/aes_tune_defaults.inc``), so the
+library's defaults are the record's winners.
 
     python -m paper_1902_05234_amd.autotune --out tune.json
+    python -m paper_1902_05234_amd.autotune --emit-defaults tuning/mi355x_sweep.json
 """
 from __future__ import annotations
 
@@ -39,9 +51,15 @@ BUCKET_SIZES = ((2 << 10, 4 << 10), (16 << 10, 64 << 10), (256 << 10, 1 << 20, 2
                 (12 << 20, 32 << 20), (256 << 20,))
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+RECORD = os.path.join(HERE, "tuning", "mi355x_sweep.json")
+DEFAULTS_INC = os.path.join(HERE, "csrc", "aes_tune_defaults.inc")
+
+
 def source_hash() -> str:
     """Hash of the device code the timings depend on (the .hip and .hpp
-    sources; host-only files and caches are left out)."""
+    sources; host-only files, the generated default table and caches are
+    left out)."""
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
@@ -52,6 +70,9 @@ def source_hash() -> str:
 
 GRAPH_TIMED_MAX = 64 << 20  # below this the host's per-call cost would dominate an eager timing
 GRAPH_LAUNCHES = 20
+SUSTAINED_TOP = 8           # variants re-timed under sustained load in the largest bucket
+SUSTAINED_SECONDS = 0.5     # back-to-back load per variant per pass (after 0.3 s of warm-up)
+SUSTAINED_PASSES = 2
 
 
 def _graph_times(torch, fn, reps):
@@ -84,6 +105,28 @@ def _times(torch, fn, reps):
     return [a.elapsed_time(b) for a, b in evs]
 
 
+def _sustained_gbps(torch, fn, nbytes, seconds=SUSTAINED_SECONDS, warm_s=0.3):
+    """GB/s of fn launched back to back for ``seconds`` after ``warm_s`` of
+    the same load (events on the launch stream around the timed launches)."""
+    fn()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter() + warm_s
+    while time.perf_counter() < t_end:
+        fn()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k = 0
+    a.record(s)
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(4):
+            fn()
+        k += 4
+    b.record(s)
+    torch.cuda.synchronize()
+    return nbytes * k / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
 def _time(torch, fn, reps):
     ms = sorted(_times(torch, fn, reps))
     return ms[len(ms) // 2]
@@ -105,13 +148,18 @@ def variants(log=None):
         log("  skipped %d bitsliced combinations (bpt does not apply; wg <= %d)" % (len(skipped), BITSLICE_MAX_WG))
 
 
-def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, rounds: int = 3, log=print):
+def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, rounds: int = 3, log=print,
+               sustained_top: int = SUSTAINED_TOP):
     """Time every variant on one (key size, direction, size); returns rows
     sorted by time.  The variants are timed in ``rounds`` interleaved passes
     (reps launches each) and ranked by the median over all launches, so a
     drift of the engine clock during the sweep does not favour whichever
     variant ran first.  Up to 64 MiB a launch is timed inside a replayed HIP
-    graph, which leaves the host's per-call cost out."""
+    graph, which leaves the host's per-call cost out.  Above that the
+    ``sustained_top`` fastest variants of this screen are timed again over
+    seconds of back-to-back launches (SUSTAINED_PASSES interleaved passes)
+    and only they are ranked, by their sustained rate; the other rows keep
+    their screen timings ("timing": "screen") and cannot win."""
     key = inputs.random_key(7, keybits)
     ks = aes.aes_expand_key(key)
     x = inputs.device_random_bytes(7, nbytes)
@@ -141,39 +189,99 @@ def tune_plain(torch, keybits: int, decrypt: bool, nbytes: int, reps: int = 10, 
     for i, v in enumerate(vs):
         t = sorted(times[i])
         ms = t[len(t) // 2]
-        rows.append({"bpt": v.bpt, "wg": v.wg, "placement": v.placement, "ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9})
+        rows.append({"bpt": v.bpt, "wg": v.wg, "placement": v.placement, "ms": ms, "GB_s": nbytes / (ms * 1e-3) / 1e9,
+                     "timing": "graph" if nbytes <= GRAPH_TIMED_MAX else "screen"})
     rows.sort(key=lambda r: r["ms"])
-    log("  %d-bit %s %d B: best bpt=%d wg=%d placement=%d %.1f GB/s (worst %.1f)" % (
+    if nbytes > GRAPH_TIMED_MAX:
+        # the library runs this bucket back to back: re-time the best few
+        # under sustained load, interleaved, and rank them by that alone
+        top = rows[:sustained_top]
+        rates = {i: [] for i in range(len(top))}
+        for _ in range(SUSTAINED_PASSES):
+            for i, r in enumerate(top):
+                v = aes.Variant(r["bpt"], r["wg"], r["placement"])
+                rates[i].append(_sustained_gbps(
+                    torch, lambda v=v: aes.aes_ecb_crypt_variant(rk, ks.nr, decrypt, x, out, v), nbytes))
+        sustained = []
+        for i, r in enumerate(top):
+            g = sorted(rates[i])[len(rates[i]) // 2] if len(rates[i]) % 2 else sum(rates[i]) / len(rates[i])
+            sustained.append(dict(r, GB_s=g, ms=nbytes / (g * 1e9) * 1e3, timing="sustained",
+                                  screen_GB_s=r["GB_s"], passes_GB_s=[round(v, 1) for v in rates[i]]))
+        sustained.sort(key=lambda r: r["ms"])
+        rows = sustained + rows[sustained_top:]
+    log("  %d-bit %s %d B: best bpt=%d wg=%d placement=%d %.1f GB/s (%s; worst %.1f)" % (
         keybits, "dec" if decrypt else "enc", nbytes, rows[0]["bpt"], rows[0]["wg"], rows[0]["placement"],
-        rows[0]["GB_s"], rows[-1]["GB_s"]))
+        rows[0]["GB_s"], rows[0]["timing"], rows[-1]["GB_s"]))
     return rows
 
 
-def tune_batch(torch, n_messages: int = 20000, chunks=(256, 1024, 4096), reps: int = 5, log=print):
+BATCH_CHUNKS = (256, 1024, 2048, 4096)
+BATCH_WGS = (256, 512, 1024)
+BATCH_PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1)
+
+
+def batch_variants():
+    """The batched search space: chunk x bytes per thread x workgroup x placement."""
+    for chunk in BATCH_CHUNKS:
+        for p in BATCH_PLACEMENTS:
+            for wg in BATCH_WGS:
+                for bpt in BPTS:
+                    yield chunk, aes.BatchConfig(bpt=bpt, wg=wg, placement=p)
+
+
+def tune_batch(torch, n_messages: int = 20000, reps: int = 3, rounds: int = 2, log=print):
+    """Time every batch variant on the mixed workload (20,000 messages, own
+    key and key size each, half encrypt, half decrypt), in ``rounds``
+    interleaved passes.  The first variant's output is checked against one
+    plain-kernel launch per message, and every other variant against that
+    output, bit for bit, before anything is timed."""
     from . import batch
     mix = inputs.message_mix(2, n_messages)
     keys = [inputs.random_key(int(s), int(b)) for s, b in zip(mix.key_seed, mix.keybits)]
     kt = batch.key_table(keys)
     in_arena = inputs.device_random_bytes(2, 16 * mix.total_blocks)
     out_arena = torch.empty_like(in_arena)
-    ref = None
+    msgs = batch.messages_from_mix(mix)
+    ref = torch.zeros_like(in_arena)
+    batch.run_per_message(msgs, [aes.aes_expand_key(k) for k in keys], in_arena, ref)
+    torch.cuda.synchronize()
+    vs = list(batch_variants())
+    prepared = []
+    for chunk, cfg in vs:
+        b = batch.prepare(msgs, kt, in_arena, out_arena, chunk_blocks=chunk, cfg=cfg)
+        out_arena.zero_()
+        b.launch()
+        torch.cuda.synchronize()
+        if b.rejected_items() or not torch.equal(out_arena, ref):
+            raise RuntimeError("batch chunk=%d %s differs from the per-message plain launches" % (chunk, cfg))
+        prepared.append(b)
+    del ref
+    times = {i: [] for i in range(len(vs))}
+    for _ in range(max(1, rounds)):
+        for i, b in enumerate(prepared):
+            times[i] += _times(torch, b.launch, reps)
     rows = []
-    for chunk in chunks:
-        for bpt in BPTS:
-            b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=chunk,
-                              cfg=aes.BatchConfig(bpt=bpt))
-            out_arena.zero_()
-            b.launch()
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = out_arena.clone()
-            elif not torch.equal(out_arena, ref):
-                raise RuntimeError("batch chunk=%d bpt=%d differs from the first configuration" % (chunk, bpt))
-            ms = _time(torch, b.launch, reps)
-            rows.append({"chunk_blocks": chunk, "bpt": bpt, "ms": ms, "GB_s": b.total_bytes / (ms * 1e-3) / 1e9})
-            log("  batch chunk=%d bpt=%d: %.1f GB/s" % (chunk, bpt, rows[-1]["GB_s"]))
+    for i, (chunk, cfg) in enumerate(vs):
+        t = sorted(times[i])
+        ms = t[len(t) // 2]
+        rows.append({"chunk_blocks": chunk, "bpt": cfg.bpt, "wg": cfg.wg, "placement": cfg.placement, "ms": ms,
+                     "GB_s": prepared[i].total_bytes / (ms * 1e-3) / 1e9})
     rows.sort(key=lambda r: r["ms"])
-    return rows
+    for r in rows[:5]:
+        log("  batch chunk=%d bpt=%d wg=%d placement=%d: %.1f GB/s" % (
+            r["chunk_blocks"], r["bpt"], r["wg"], r["placement"], r["GB_s"]))
+    w = rows[0]
+    return {"winner": {k: w[k] for k in ("chunk_blocks", "bpt", "wg", "placement")}, "GB_s": round(w["GB_s"], 1),
+            "messages": n_messages, "bytes": prepared[0].total_bytes, "all": rows}
+
+
+def batch_winner(record: dict):
+    """(chunk_blocks, BatchConfig) of a record's batched winner, or None."""
+    b = record.get("batch")
+    if not isinstance(b, dict) or "winner" not in b:
+        return None
+    w = b["winner"]
+    return w["chunk_blocks"], aes.BatchConfig(bpt=w["bpt"], wg=w["wg"], placement=w["placement"])
 
 
 def bucket_winner(per_size: dict) -> dict:
@@ -191,11 +299,20 @@ def bucket_winner(per_size: dict) -> dict:
     return {"bpt": v[0], "wg": v[1], "placement": v[2], "worst_ratio": round(score[v], 4)}
 
 
+def device_identity(torch=None):
+    """(name, architecture) of the current device."""
+    if torch is None:
+        import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return p.name, getattr(p, "gcnArchName", "")
+
+
 def run(buckets=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10, rounds=3, log=print):
     """buckets: one tuple of sizes per tuning bucket (the library's bucket of
     each tuple's sizes must agree)."""
     import torch
-    rec = {"device": torch.cuda.get_device_properties(0).name, "source_hash": source_hash(),
+    name, arch = device_identity(torch)
+    rec = {"device": name, "arch": arch, "source_hash": source_hash(), "hip": torch.version.hip,
            "created": time.strftime("%Y-%m-%dT%H:%M:%S"), "plain": {}, "batch": None}
     for kb in key_sizes:
         for dec in (False, True):
@@ -214,16 +331,84 @@ def run(buckets=BUCKET_SIZES, key_sizes=(128, 192, 256), batch_too=True, reps=10
     return rec
 
 
-def apply(record: dict):
-    """Install the plain-path winners of a record into the library's tuning table."""
-    n = 0
+class RecordMismatch(RuntimeError):
+    """A tuning record made on another device or for other kernel sources."""
+
+
+def record_mismatch(record: dict, device=None, arch=None, src_hash=None):
+    """Reasons the record does not describe this device and these kernels
+    (empty when it does).  device/arch: the current device's name and
+    architecture (None: not checked); src_hash: defaults to source_hash()."""
+    why = []
+    want = source_hash() if src_hash is None else src_hash
+    if record.get("source_hash") != want:
+        why.append("made for kernel sources %s, these are %s" % (record.get("source_hash"), want))
+    if device is not None and record.get("device") != device:
+        why.append("made on device %r, this is %r" % (record.get("device"), device))
+    if arch is not None and record.get("arch") is not None and record.get("arch") != arch:
+        why.append("made for architecture %r, this is %r" % (record.get("arch"), arch))
+    return why
+
+
+def winners(record: dict):
+    """{(nr, decrypt, bucket): (bpt, wg, placement)} of a record's plain path."""
+    out = {}
     for k, v in record.get("plain", {}).items():
         kb, d, nbytes = k.split("/")
+        sizes = v.get("sizes") or [int(nbytes)]
+        bucket = aes.aes_size_bucket(max(sizes) // 16)
         w = v["winner"]
-        nr = {128: 10, 192: 12, 256: 14}[int(kb)]
-        aes.aes_tune_set(nr, d == "dec", int(nbytes) // 16, aes.Variant(w["bpt"], w["wg"], w["placement"]))
+        out[({128: 10, 192: 12, 256: 14}[int(kb)], d == "dec", bucket)] = (w["bpt"], w["wg"], w["placement"])
+    return out
+
+
+def apply(record: dict, force: bool = False):
+    """Install the plain-path winners of a record into the library's tuning
+    table.  A record made on another device or architecture, or for other
+    kernel sources, is refused (RecordMismatch) unless ``force``."""
+    if not force:
+        try:
+            name, arch = device_identity()
+        except Exception:  # no device to compare with: only the sources are checked
+            name = arch = None
+        why = record_mismatch(record, name, arch)
+        if why:
+            raise RecordMismatch("tuning record refused (%s); pass force=True to install it anyway" % "; ".join(why))
+    n = 0
+    for (nr, dec, bucket), (bpt, wg, pl) in winners(record).items():
+        aes.aes_tune_set(nr, dec, _bucket_size(bucket), aes.Variant(bpt, wg, pl))
         n += 1
     return n
+
+
+def _bucket_size(bucket: int) -> int:
+    """A block count that lies in tuning bucket ``bucket``."""
+    return BUCKET_SIZES[bucket][-1] // 16
+
+
+def emit_defaults(record: dict) -> str:
+    """The compiled-in default table (csrc/aes_tune_defaults.inc) that
+    reproduces a record's plain-path winners, one entry per key size,
+    direction and size bucket."""
+    w = winners(record)
+    lines = ["// aes_tune_defaults.inc -- generated by `python -m paper_1902_05234_amd.autotune",
+             "// --emit-defaults` from tuning/%s (device %s, kernel sources %s, %s);" % (
+                 os.path.basename(RECORD), record.get("device"), record.get("source_hash"), record.get("created")),
+             "// do not edit: regenerate it from a new record instead.",
+             "// kTuneDefaults[nr index][decrypt][size bucket] = {bytes per thread / 16, workgroup, placement}",
+             "static constexpr TuneDefault kTuneDefaults[3][2][AES_SIZE_BUCKETS] = {"]
+    for ni, nr in enumerate((10, 12, 14)):
+        lines.append("    {  // Nr = %d" % nr)
+        for dec in (False, True):
+            cells = []
+            for b in range(aes.AES_SIZE_BUCKETS):
+                if (nr, dec, b) not in w:
+                    raise ValueError("record has no winner for Nr=%d %s bucket %d" % (nr, "dec" if dec else "enc", b))
+                cells.append("{%d, %d, %d}" % w[(nr, dec, b)])
+            lines.append("        {%s},  // %s" % (", ".join(cells), "decrypt" if dec else "encrypt"))
+        lines.append("    },")
+    lines.append("};")
+    return "\n".join(lines) + "\n"
 
 
 def load(path: str) -> dict:
@@ -240,8 +425,25 @@ def main(argv=None):
     ap.add_argument("--rounds", type=int, default=3, help="interleaved passes over the variants")
     ap.add_argument("--sizes", default=None,
                     help="comma-separated byte sizes, each tuned on its own (default: two or three per size bucket)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="tune the batched mix only and store it into the record given by --out (which must exist)")
+    ap.add_argument("--emit-defaults", metavar="RECORD", default=None,
+                    help="write csrc/aes_tune_defaults.inc from RECORD (no GPU needed) and exit")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    if a.emit_defaults:
+        with open(DEFAULTS_INC, "w") as f:
+            f.write(emit_defaults(load(a.emit_defaults)))
+        log("wrote", DEFAULTS_INC)
+        return
+    if a.batch_only:
+        import torch
+        rec = load(a.out)
+        rec["batch"] = tune_batch(torch, log=log)
+        with open(a.out, "w") as f:
+            json.dump(rec, f, indent=1)
+        log("wrote", a.out)
+        return
     if a.quick:
         rec = run(buckets=((256 << 20,),), key_sizes=(256,), batch_too=not a.no_batch, reps=a.reps, rounds=a.rounds,
                   log=log)

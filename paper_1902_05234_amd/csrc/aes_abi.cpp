@@ -84,33 +84,26 @@ struct TuneEntry {
 };
 TuneEntry g_tune[3][2][AES_SIZE_BUCKETS];  // [nr index][decrypt][bucket]
 
-// Compiled-in defaults from MI355X autotune sweeps (paper_1902_05234_amd.autotune,
-// variants timed in interleaved passes at two or three sizes per bucket;
-// record in tuning/mi355x_sweep.json): up to 2 MiB launches are bound by
-// latency and prefer the smallest table fill (one table, 512-thread
-// workgroups); up to 32 MiB the 2-table placement (two 1024-thread
-// workgroups per CU) with 16 bytes per thread wins, since 32 or 64 bytes
-// per thread leave waves without a unit at these sizes; above that the
-// 4-table placement with 64 bytes per thread is 4-8 % faster at 256 MiB
-// for every key size and both directions.
+// Compiled-in defaults: the winners of the MI355X autotune record
+// (paper_1902_05234_amd/tuning/mi355x_sweep.json), written into
+// aes_tune_defaults.inc by `python -m paper_1902_05234_amd.autotune
+// --emit-defaults`; a CPU test checks that the two agree.
+struct TuneDefault {
+    int bpt, wg, placement;
+};
+#include "aes_tune_defaults.inc"
+
 struct TuneDefaults {
-    static void set(TuneEntry& t, int bpt, int wg, int placement)
-    {
-        t.bpt.store(bpt);
-        t.wg.store(wg);
-        t.placement.store(placement);
-    }
     TuneDefaults()
     {
-        for (int n = 0; n < 3; ++n) {
-            for (int d = 0; d < 2; ++d) {
-                for (int b = 0; b < 3; ++b)
-                    set(g_tune[n][d][b], 1, 512, AES_PLACEMENT_TTABLE1);
-                set(g_tune[n][d][3], 1, 1024, AES_PLACEMENT_TTABLE2);
-                set(g_tune[n][d][4], 1, 1024, AES_PLACEMENT_TTABLE2);
-                set(g_tune[n][d][5], 4, 1024, AES_PLACEMENT_TTABLE4);
-            }
-        }
+        for (int n = 0; n < 3; ++n)
+            for (int d = 0; d < 2; ++d)
+                for (int b = 0; b < AES_SIZE_BUCKETS; ++b) {
+                    const TuneDefault& t = kTuneDefaults[n][d][b];
+                    g_tune[n][d][b].bpt.store(t.bpt);
+                    g_tune[n][d][b].wg.store(t.wg);
+                    g_tune[n][d][b].placement.store(t.placement);
+                }
     }
 } g_tune_defaults;
 
@@ -141,8 +134,11 @@ int check_buffers(const void* in, void* out, size_t nblocks)
 
 int check_variant(const aes_variant* v)
 {
-    if (v->bpt != 1 && v->bpt != 2 && v->bpt != 4)
-        return fail(AES_EINVAL, "bpt must be 1, 2 or 4 (16, 32 or 64 bytes per thread), got %d", v->bpt);
+    if (v->bpt != AES_BPT_COLUMN && v->bpt != 1 && v->bpt != 2 && v->bpt != 4)
+        return fail(AES_EINVAL, "bpt must be 1, 2 or 4 (16, 32 or 64 bytes per thread) or AES_BPT_COLUMN, got %d",
+                    v->bpt);
+    if (v->bpt == AES_BPT_COLUMN && v->placement == AES_PLACEMENT_BITSLICED)
+        return fail(AES_EINVAL, "one column per lane (AES_BPT_COLUMN) runs on the table placements only");
     if (v->wg < 64 || v->wg > 1024 || (v->wg % 64) != 0)
         return fail(AES_EINVAL, "workgroup size must be a multiple of 64 in [64, 1024], got %d", v->wg);
     if (v->placement != AES_PLACEMENT_TTABLE4 && v->placement != AES_PLACEMENT_TTABLE2 &&
@@ -184,8 +180,10 @@ int run_ecb(const uint32_t* rk, int nr, bool decrypt, const void* in, void* out,
     return AES_OK;
 }
 
-// CTR and CBC run on the table placements; a bitsliced tuning entry (ECB
-// only) is replaced by the 2-table kernel with 32 bytes per thread.
+// CTR and CBC run on the whole-state table kernels; a bitsliced tuning entry
+// (ECB only) is replaced by the 2-table kernel with 32 bytes per thread, and
+// a one-column-per-lane entry (ECB only) by the same placement with one
+// block per thread.
 void table_variant(aes_variant* v)
 {
     if (v->placement == AES_PLACEMENT_BITSLICED) {
@@ -193,6 +191,8 @@ void table_variant(aes_variant* v)
         v->bpt = 2;
         v->wg = 1024;
     }
+    if (v->bpt == AES_BPT_COLUMN)
+        v->bpt = 1;
 }
 
 int run_ctr(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset, const void* in, void* out,
@@ -215,8 +215,8 @@ int run_ctr(const uint32_t* rk, int nr, const uint8_t* iv, uint64_t block_offset
     int rc = check_variant(v);
     if (rc != AES_OK)
         return rc;
-    if (v->placement == AES_PLACEMENT_BITSLICED)
-        return fail(AES_EINVAL, "CTR runs on the table placements only");
+    if (v->placement == AES_PLACEMENT_BITSLICED || v->bpt == AES_BPT_COLUMN)
+        return fail(AES_EINVAL, "CTR runs on the whole-state table kernels only (no bitsliced or column variant)");
     // c0 = iv + block_offset as a 128-bit big-endian sum
     Counter128 c0{0, 0};
     for (int i = 0; i < 8; ++i) {
@@ -255,8 +255,9 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     rc = check_variant(v);
     if (rc != AES_OK)
         return rc;
-    if (v->placement == AES_PLACEMENT_BITSLICED)
-        return fail(AES_EINVAL, "CBC decryption runs on the table placements only");
+    if (v->placement == AES_PLACEMENT_BITSLICED || v->bpt == AES_BPT_COLUMN)
+        return fail(AES_EINVAL,
+                    "CBC decryption runs on the whole-state table kernels only (no bitsliced or column variant)");
     RoundKeys keys{};
     std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
     int cus = device_cu_count();

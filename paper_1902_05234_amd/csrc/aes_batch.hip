@@ -65,7 +65,7 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
             x[j] = crypt_block<NR, kDecrypt, PL>(x[j], lds, lb, key);
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
-            out[first + 64u * j] = x[j];
+            store_block(out + first + 64u * j, x[j]);
     }
     const uint32_t b0 = full * span;
     if (b0 < nblocks) {
@@ -73,7 +73,7 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
         for (int j = 0; j < BPT; ++j) {
             const uint32_t b = b0 + lane + 64u * j;
             if (b < nblocks)
-                out[b] = crypt_block<NR, kDecrypt, PL>(in[b], lds, lb, key);
+                store_block(out + b, crypt_block<NR, kDecrypt, PL>(in[b], lds, lb, key));
         }
     }
 }

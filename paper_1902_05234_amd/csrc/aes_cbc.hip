@@ -57,7 +57,7 @@ __global__ __launch_bounds__(1024) void cbc_dec_kernel(const uint4* __restrict__
         }
 #pragma unroll
         for (int k = 0; k < BPT; ++k)
-            out[first + 64u * k] = xor4c(crypt_block<NR, true, PL>(cur[k], lds, lb, key), prv[k]);
+            store_block(out + first + 64u * k, xor4c(crypt_block<NR, true, PL>(cur[k], lds, lb, key), prv[k]));
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             cur[k] = nxt[k];
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(1024) void cbc_dec_kernel(const uint4* __restrict__
         for (int k = 0; k < BPT; ++k) {
             const uint64_t b = wv * span + lane + 64u * k;
             if (b < nblocks)
-                out[b] = xor4c(crypt_block<NR, true, PL>(in[b], lds, lb, key), prev(b));
+                store_block(out + b, xor4c(crypt_block<NR, true, PL>(in[b], lds, lb, key), prev(b)));
         }
     }
 }

@@ -6,8 +6,8 @@
 // so every block is independent, as in ECB.  Each lane builds its counter
 // block from the block index (no memory read), runs the encryption rounds
 // and XORs the result into the data it loaded: the same 32 bytes of HBM per
-// block and the same LDS lookups as an ECB encryption.  Decryption is the
-// same operation.  A partial last block is read and written byte by byte and
+// block as an ECB encryption, and fewer LDS lookups (counter-mode caching,
+// below).  Decryption is the same operation.  A partial last block is read and written byte by byte and
 // uses the leading bytes of its key-stream block.
 #include "aes_ecb_kernel.hpp"
 
@@ -113,7 +113,7 @@ __device__ __forceinline__ void ctr_edge_unit(const uint4* __restrict__ in, uint
             continue;
         const uint64_t b = i - d;
         if (b < nfull) {
-            out[b] = xor4(in[b], crypt_block<NR, false, PL>(counter_state(c0, b), lds, lb, key));
+            store_block(out + b, xor4(in[b], crypt_block<NR, false, PL>(counter_state(c0, b), lds, lb, key)));
         } else if (b < nblocks) {
             const uint4 ks = crypt_block<NR, false, PL>(counter_state(c0, b), lds, lb, key);
             const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(1024) void ctr_kernel(const uint4* __restrict__ in,
         for (int k = 0; k < BPT; ++k) {
             // slot lane + 64k: only byte 15 (bits 24..31 of word 3) moves, with no carry
             const uint32_t w3k = w3 + ((lane + 64u * k) << 24);
-            out[first + 64u * k] = xor4(cur[k], ctr_keystream<NR, PL>(c, w3k, lds, lb, rk.w[3], key));
+            store_block(out + first + 64u * k, xor4(cur[k], ctr_keystream<NR, PL>(c, w3k, lds, lb, rk.w[3], key)));
         }
 #pragma unroll
         for (int k = 0; k < BPT; ++k)

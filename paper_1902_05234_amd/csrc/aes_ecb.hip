@@ -14,9 +14,14 @@ hipError_t launch_ecb_p2(const LaunchShape&, int, bool, const void*, void*, uint
 hipError_t launch_ecb_p1(const LaunchShape&, int, bool, const void*, void*, uint64_t, const RoundKeys&, int,
                          hipStream_t);
 
+hipError_t launch_ecb_col(const LaunchShape&, int, int, bool, const void*, void*, uint64_t, const RoundKeys&, int,
+                          hipStream_t);
+
 hipError_t launch_ecb(const LaunchShape& shape, int placement, int nr, bool decrypt, const void* in, void* out,
                       uint64_t nblocks, const RoundKeys& rk, int cus, hipStream_t stream)
 {
+    if (shape.bpt == AES_BPT_COLUMN)
+        return launch_ecb_col(shape, placement, nr, decrypt, in, out, nblocks, rk, cus, stream);
     switch (placement) {
     case 0: return launch_ecb_p4(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);
     case 1: return launch_ecb_p2(shape, nr, decrypt, in, out, nblocks, rk, cus, stream);

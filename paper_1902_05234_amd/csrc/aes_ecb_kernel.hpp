@@ -60,7 +60,7 @@ __global__ __launch_bounds__(1024) void ecb_kernel(const uint4* __restrict__ in,
             cur[k] = crypt_block<NR, kDecrypt, PL>(cur[k], lds, lb, key);
 #pragma unroll
         for (int k = 0; k < BPT; ++k)
-            out[first + 64u * k] = cur[k];
+            store_block(out + first + 64u * k, cur[k]);
 #pragma unroll
         for (int k = 0; k < BPT; ++k)
             cur[k] = nxt[k];
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(1024) void ecb_kernel(const uint4* __restrict__ in,
         for (int k = 0; k < BPT; ++k) {
             const uint64_t b = wv * span + lane + 64u * k;
             if (b < nblocks)
-                out[b] = crypt_block<NR, kDecrypt, PL>(in[b], lds, lb, key);
+                store_block(out + b, crypt_block<NR, kDecrypt, PL>(in[b], lds, lb, key));
         }
     }
 }

@@ -59,7 +59,7 @@ def test_ragged_sizes_all_key_sizes(oracle_lib, keybits, nblocks):
     assert_same(to_host(gpu_dec(ks, xd)), oracle_lib.ecb_decrypt(key, x), "dec %d-bit n=%d" % (keybits, nblocks))
 
 
-VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=g) for p in (0, 1, 2) for b in (1, 2, 4)
+VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=g) for p in (0, 1, 2) for b in (aes.AES_BPT_COLUMN, 1, 2, 4)
             for w in (64, 128, 256, 512, 1024) for g in (0, 3)]
 
 
@@ -77,6 +77,30 @@ def test_every_variant(oracle_lib, variant):
         aes.aes_ecb_crypt_variant(rk, ks.nr, dec, xd, out, variant)
         want = oracle_lib.ecb_decrypt(key, x) if dec else oracle_lib.ecb_encrypt(key, x)
         assert_same(to_host(out), want, "%s %d-bit dec=%s" % (variant, keybits, dec))
+
+
+@pytest.mark.parametrize("placement", [0, 1, 2])
+def test_column_variant_every_key_size_and_direction(oracle_lib, placement):
+    """One column per lane (four lanes per block): every key size in both
+    directions, block counts around the 16-block wave unit and the quads of
+    a ragged last unit, in place, and a grid of one workgroup that walks the
+    whole buffer."""
+    torch = cuda()
+    for nblocks in (1, 3, 15, 16, 17, 63, 1000, 4096 + 5):
+        x = inputs.random_bytes(700 + nblocks, 16 * nblocks)
+        for keybits in (128, 192, 256):
+            key = inputs.random_key(701 + keybits, keybits)
+            ks = aes.aes_expand_key(key)
+            for dec, wg, grid in ((False, 256, 0), (True, 1024, 0), (False, 64, 1), (True, 128, 1)):
+                v = aes.Variant(bpt=aes.AES_BPT_COLUMN, wg=wg, placement=placement, grid=grid)
+                xd = to_dev(x)
+                out = torch.empty_like(xd)
+                rk = ks.rk_dec if dec else ks.rk_enc
+                aes.aes_ecb_crypt_variant(rk, ks.nr, dec, xd, out, v)
+                want = oracle_lib.ecb_decrypt(key, x) if dec else oracle_lib.ecb_encrypt(key, x)
+                assert_same(to_host(out), want, "%s %d-bit dec=%s %d blocks" % (v, keybits, dec, nblocks))
+                aes.aes_ecb_crypt_variant(rk, ks.nr, dec, xd, xd, v)  # in place
+                assert_same(to_host(xd), want, "in place %s %d-bit dec=%s %d blocks" % (v, keybits, dec, nblocks))
 
 
 def test_in_place_and_prefix(oracle_lib):

@@ -214,7 +214,8 @@ def test_ecb_argument_checks_before_any_device_call():
     assert lib.aes_ecb_encrypt(rk, 10, A, B + 8, 4, None) == aes.AES_EALIGN
     assert lib.aes_ecb_encrypt(rk, 10, A, A + 16, 4, None) == aes.AES_EINVAL  # partial overlap
     assert "overlap" in aes.aes_last_error()
-    bad = [aes.Variant(bpt=3), aes.Variant(wg=100), aes.Variant(wg=2048), aes.Variant(placement=7), aes.Variant(placement=3), aes.Variant(grid=-1)]
+    bad = [aes.Variant(bpt=3), aes.Variant(wg=100), aes.Variant(wg=2048), aes.Variant(placement=7), aes.Variant(placement=3), aes.Variant(grid=-1),
+           aes.Variant(bpt=aes.AES_BPT_COLUMN, placement=aes.AES_PLACEMENT_BITSLICED)]
     for v in bad:
         cv = v._c()
         assert lib.aes_ecb_crypt_variant(rk, 10, 0, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
@@ -235,7 +236,8 @@ def test_ctr_argument_checks_before_any_device_call():
     assert lib.aes_ctr_crypt(rk, 10, iv, 0, A + 1, B, 5, None) == aes.AES_EALIGN
     assert lib.aes_ctr_crypt(rk, 10, iv, 0, A, A + 16, 17, None) == aes.AES_EINVAL  # partial overlap
     assert "overlap" in aes.aes_last_error()
-    for v in [aes.Variant(bpt=8), aes.Variant(wg=32), aes.Variant(placement=5), aes.Variant(grid=-2)]:
+    for v in [aes.Variant(bpt=8), aes.Variant(wg=32), aes.Variant(placement=5), aes.Variant(grid=-2),
+              aes.Variant(bpt=aes.AES_BPT_COLUMN)]:
         cv = v._c()
         assert lib.aes_ctr_crypt_variant(rk, 10, iv, 0, A, B, 64, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
     assert lib.aes_ctr_crypt_variant(rk, 10, iv, 0, A, B, 64, None, None) == aes.AES_EINVAL
@@ -254,8 +256,9 @@ def test_cbc_argument_checks_before_any_device_call():
     assert "in place" in aes.aes_last_error()
     assert lib.aes_cbc_decrypt(rk, 10, iv, A, A + 32, 4, None) == aes.AES_EINVAL    # partial overlap
     assert lib.aes_cbc_decrypt(rk, 10, iv, A + 8, B, 4, None) == aes.AES_EALIGN
-    cv = aes.Variant(bpt=3)._c()
-    assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL
+    for v in (aes.Variant(bpt=3), aes.Variant(bpt=aes.AES_BPT_COLUMN)):
+        cv = v._c()
+        assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, aes.ctypes.byref(cv), None) == aes.AES_EINVAL, v
     assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, None, None) == aes.AES_EINVAL
 
 
@@ -424,25 +427,45 @@ def test_batch_plan_rejects_block_ranges_and_item_counts_that_wrap():
     assert got["in_block"].tolist() == [k * aes.AES_MAX_ITEM_BLOCKS for k in range(4)]
 
 
-def test_tune_file_from_environment_replaces_defaults(tmp_path):
-    """AESGPU_TUNE_FILE installs an autotune record when the library loads."""
-    import json
+def _tune_get_in_child(env_extra):
+    """aes_tune_get of three (key size, direction, size) cases in a fresh
+    process whose environment adds env_extra; (returncode, values, stderr)."""
     import subprocess
     import sys
-    rec = {"plain": {"256/enc/268435456": {"winner": {"bpt": 1, "wg": 256, "placement": 1}},
-                     "128/dec/4096": {"winner": {"bpt": 2, "wg": 128, "placement": 0}}}}
-    path = tmp_path / "tune.json"
-    path.write_text(json.dumps(rec))
     code = ("from paper_1902_05234_amd import aes\n"
             "a = aes.aes_tune_get(14, False, 268435456 // 16)\n"
             "b = aes.aes_tune_get(10, True, 4096 // 16)\n"
             "c = aes.aes_tune_get(10, False, 268435456 // 16)\n"
             "print(a.bpt, a.wg, a.placement, b.bpt, b.wg, b.placement, c.bpt, c.wg, c.placement)\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ, AESGPU_TUNE_FILE=str(path))
+    env = {k: v for k, v in os.environ.items() if k not in (aes.TUNE_FILE_ENV, aes.TUNE_FORCE_ENV)}
+    env.update(env_extra)
     out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=120)
-    assert out.returncode == 0, out.stderr
-    got = [int(x) for x in out.stdout.split()]
+    vals = [int(x) for x in out.stdout.split()] if out.returncode == 0 else None
+    return out.returncode, vals, out.stderr
+
+
+def test_tune_file_from_environment_replaces_defaults(tmp_path):
+    """AESGPU_TUNE_FILE installs an autotune record when the library loads;
+    a record made for other kernel sources is refused unless forced."""
+    import json
+    from paper_1902_05234_amd import autotune
+    rec = {"source_hash": autotune.source_hash(),
+           "plain": {"256/enc/268435456": {"winner": {"bpt": 1, "wg": 256, "placement": 1}},
+                     "128/dec/4096": {"winner": {"bpt": 2, "wg": 128, "placement": 0}}}}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps(rec))
+    rc, default, err = _tune_get_in_child({})
+    assert rc == 0, err
+    rc, got, err = _tune_get_in_child({aes.TUNE_FILE_ENV: str(path)})
+    assert rc == 0, err
     # the two covered buckets take the record's variants; AES-128 encrypt of
-    # the same size keeps the compiled-in default (4 tables, 64 B, 1024)
-    assert got == [1, 256, 1, 2, 128, 0, 4, 1024, 0]
+    # the same size keeps the compiled-in default
+    assert got == [1, 256, 1, 2, 128, 0] + default[6:]
+    stale = dict(rec, source_hash="0123456789abcdef")
+    path.write_text(json.dumps(stale))
+    rc, _, err = _tune_get_in_child({aes.TUNE_FILE_ENV: str(path)})
+    assert rc != 0 and "RecordMismatch" in err and "kernel sources" in err
+    rc, got, err = _tune_get_in_child({aes.TUNE_FILE_ENV: str(path), aes.TUNE_FORCE_ENV: "1"})
+    assert rc == 0, err
+    assert got == [1, 256, 1, 2, 128, 0] + default[6:]
