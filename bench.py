@@ -550,9 +550,10 @@ def batched(torch, aes, inputs, bulk_rates):
     total = mix.total_blocks
     in_arena = inputs.device_random_bytes(2, 16 * total)
     out_arena = torch.empty_like(in_arena)
-    # work-item size and blocks per thread from the autotune record (tuning/mi355x_sweep.json)
-    b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=4096,
-                      cfg=aes.BatchConfig(bpt=4))
+    # work-item size and batch kernel variant: the autotune record's winner
+    from paper_1902_05234_amd import autotune
+    chunk, cfg = autotune.batch_winner(autotune.load(autotune.RECORD))
+    b = batch.prepare(batch.messages_from_mix(mix), kt, in_arena, out_arena, chunk_blocks=chunk, cfg=cfg)
     b.capture()
     warm(torch, b.replay)
     tm = Timer(torch)
@@ -579,7 +580,8 @@ def batched(torch, aes, inputs, bulk_rates):
     return {"messages": len(mix), "bytes": nbytes, "GB_s": round(batched_gbps, 1), "ms": round(ms, 3),
             "bulk_equivalent_GB_s": round(bulk_eq, 1), "vs_bulk": round(batched_gbps / bulk_eq, 4),
             "per_message_launch_GB_s": round(nbytes / per_msg_s / 1e9, 2),
-            "rejected_items": b.rejected_items(), "chunk_blocks": 4096, "bpt": 4, "graph": True}
+            "rejected_items": b.rejected_items(), "chunk_blocks": chunk, "bpt": cfg.bpt, "wg": cfg.wg,
+            "placement": cfg.placement, "variant_from": "tuning record batch winner", "graph": True}
 
 
 SATURATION_RHO = 1.5
@@ -753,6 +755,76 @@ def profile_mid(torch, aes, inputs, replays=10):
         log("%s: %.2f us per launch (graph replay, events)" % (name, ms * 1e3))
 
 
+def corun(torch, aes, inputs, sweep: bool):
+    """The bitsliced kernel (VALU only, no LDS) on one stream beside the
+    4-table kernel (LDS-bound) on another, each on its share of one 1 GiB
+    buffer: can the VALU that the table kernel leaves idle carry blocks?
+    sweep: sustained GB/s for bitsliced shares 0 ... 0.24, two interleaved
+    passes, and the bitsliced kernel alone; else 30 steps at share 0.10 (for
+    a kernel trace that shows whether the two kernels overlap)."""
+    x = inputs.device_random_bytes(1, GiB)
+    y = torch.empty_like(x)
+    ref = torch.empty_like(x)
+    ks = aes.aes_expand_key(inputs.random_key(1, 128))
+    nblocks = GiB // 16
+    v4 = aes.Variant(bpt=4, wg=1024, placement=aes.AES_PLACEMENT_TTABLE4)
+    vb = aes.Variant(bpt=1, wg=256, placement=aes.AES_PLACEMENT_BITSLICED,
+                     grid=torch.cuda.get_device_properties(0).multi_processor_count)
+    aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x, ref, v4)
+    cur = torch.cuda.current_stream()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def step(nb):
+        sa.wait_stream(cur)
+        sb.wait_stream(cur)
+        if nb:
+            with torch.cuda.stream(sa):  # first, so it is resident when the table kernel arrives
+                aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x[:nb * 16], y[:nb * 16], vb)
+        with torch.cuda.stream(sb):
+            aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x[nb * 16:], y[nb * 16:], v4)
+        cur.wait_stream(sa)
+        cur.wait_stream(sb)
+
+    def share(f):
+        return (int(f * nblocks) // 8192) * 8192
+
+    def rate(nb, seconds=1.0):
+        step(nb)
+        torch.cuda.synchronize()
+        if not torch.equal(y, ref):
+            raise RuntimeError("co-run output differs from the 4-table kernel alone (share %d blocks)" % nb)
+        warm(torch, lambda: step(nb), 0.5)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(cur)
+        k, t_end = 0, time.perf_counter() + seconds
+        while time.perf_counter() < t_end:
+            step(nb)
+            k += 1
+        b.record(cur)
+        torch.cuda.synchronize()
+        return GiB * k / (a.elapsed_time(b) * 1e-3) / 1e9
+
+    if not sweep:
+        nb = share(0.10)
+        step(nb)
+        torch.cuda.synchronize()
+        if not torch.equal(y, ref):
+            raise RuntimeError("co-run output differs from the 4-table kernel alone")
+        for _ in range(30):
+            step(nb)
+        torch.cuda.synchronize()
+        log("co-run trace steps done: bitsliced share %d blocks" % nb)
+        return
+    for p in range(2):
+        log("co-run pass %d: %s" % (p, "  ".join("f=%.2f %.1f GB/s" % (f, rate(share(f)))
+                                                 for f in (0.0, 0.04, 0.08, 0.12, 0.16, 0.24))))
+    t = Timer(torch)
+    aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x, y, vb)
+    for _ in range(20):
+        t.run(lambda: aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x, y, vb))
+    log("bitsliced kernel alone: %.1f GB/s" % (GiB / (sorted(t.ms())[10] * 1e-3) / 1e9))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -768,9 +840,13 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host-inclusive file-size sweep")
     ap.add_argument("--serve-levels", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9,1.0")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid"), default=None,
+    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid", "corun", "corun-sweep", "ctr"),
+                    default=None,
                     help="bulk: only a few copy and 1 GiB launches; mid: graph-replayed AES-128 encryptions of "
-                         "64 KiB ... 32 MiB and of a 16-byte copy (for rocprofv3 kernel traces)")
+                         "64 KiB ... 32 MiB and of a 16-byte copy (for rocprofv3 kernel traces); corun: the "
+                         "bitsliced kernel beside the 4-table kernel on two streams, 30 steps (for a kernel "
+                         "trace); corun-sweep: their sustained rates over bitsliced shares 0 ... 0.24; ctr: 1 GiB CTR and ECB "
+                         "encryptions in turn (for counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -791,6 +867,22 @@ def main():
 
     if args.profile == "mid":
         profile_mid(torch, aes, inputs)
+        return
+    if args.profile in ("corun", "corun-sweep"):
+        corun(torch, aes, inputs, args.profile == "corun-sweep")
+        return
+    if args.profile == "ctr":
+        # counter mode beside ECB encryption, 1 GiB each, tuned defaults (for
+        # counters: LDS instructions per block with and without the caching)
+        x = inputs.device_random_bytes(1, GiB)
+        y = torch.empty_like(x)
+        ks = aes.aes_expand_key(inputs.random_key(1, 128))
+        iv = bytes(range(16))
+        for _ in range(max(1, args.steps)):
+            aes.aes_ctr_crypt(ks.rk_enc, ks.nr, iv, 0, x, y)
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
+        torch.cuda.synchronize()
+        log("ctr profile launches done")
         return
     if args.profile:
         x = inputs.device_random_bytes(1, GiB)

@@ -108,9 +108,10 @@ int aes_ecb_crypt_variant(const uint32_t *rk, int nr, int decrypt, const void *i
 
 /* Tuning table used by aes_ecb_encrypt/decrypt: one variant per (nr,
  * direction, size bucket of nblocks).  Buckets: <=256 blocks (4 KiB),
- * <=4096 (64 KiB), <=131072 (2 MiB), <=524288 (8 MiB), <=2097152 (32 MiB), larger.
+ * <=4096 (64 KiB), <=32768 (512 KiB), <=131072 (2 MiB), <=524288 (8 MiB),
+ * <=2097152 (32 MiB), larger.
  * aes_tune_set is process-wide and thread-safe; grid is ignored. */
-#define AES_SIZE_BUCKETS 6
+#define AES_SIZE_BUCKETS 7
 int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant *v);
 int aes_tune_get(int nr, int decrypt, size_t nblocks, aes_variant *v);
 int aes_size_bucket(size_t nblocks);

@@ -24,7 +24,7 @@ AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0,
 AES_PLACEMENT_TTABLE4, AES_PLACEMENT_TTABLE2, AES_PLACEMENT_TTABLE1, AES_PLACEMENT_BITSLICED = 0, 1, 2, 3
 AES_BPT_COLUMN = 0  # Variant.bpt: one column word per lane, four lanes per block
 AES_KEY_SLOT_WORDS, AES_KEY_SLOT_ENC, AES_KEY_SLOT_DEC, AES_KEY_SLOT_NR = 128, 0, 64, 124
-AES_SIZE_BUCKETS = 6
+AES_SIZE_BUCKETS = 7
 
 MSG_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u8"),
                       ("key_slot", "<u4"), ("decrypt", "<u4")])

@@ -1,6 +1,7 @@
 """Autotuner for the plain and batched ECB kernels.
 
-Search space (plain path): blocks per thread {1, 2, 4} (16/32/64 bytes per
+Search space (plain path): bytes per thread {4, 16, 32, 64} (4: one column
+word per lane, four lanes per block; 16-64: one to four whole blocks per
 thread) x workgroup size {64, 128, 256, 512, 1024} x table placement (the
 placements built into the library).  Every variant must reproduce the
 reference variant's output bit for bit (and decrypt back to the input)
@@ -41,14 +42,15 @@ import time
 from . import aes, inputs
 
 BPTS = (1, 2, 4)
+PLAIN_BPTS = (aes.AES_BPT_COLUMN,) + BPTS  # the plain path also has one column per lane (4 bytes per thread)
 WGS = (64, 128, 256, 512, 1024)
 PLACEMENTS = (aes.AES_PLACEMENT_TTABLE4, aes.AES_PLACEMENT_TTABLE2, aes.AES_PLACEMENT_TTABLE1,
               aes.AES_PLACEMENT_BITSLICED)
 BITSLICE_MAX_WG = 256
 # sizes timed for each tuning bucket (bytes; bucket limits in aesgpu.h: 4 KiB,
-# 64 KiB, 2 MiB, 8 MiB, 32 MiB, larger)
-BUCKET_SIZES = ((2 << 10, 4 << 10), (16 << 10, 64 << 10), (256 << 10, 1 << 20, 2 << 20), (3 << 20, 8 << 20),
-                (12 << 20, 32 << 20), (256 << 20,))
+# 64 KiB, 512 KiB, 2 MiB, 8 MiB, 32 MiB, larger)
+BUCKET_SIZES = ((2 << 10, 4 << 10), (16 << 10, 64 << 10), (256 << 10, 512 << 10), (1 << 20, 2 << 20),
+                (3 << 20, 8 << 20), (12 << 20, 32 << 20), (256 << 20,))
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -138,7 +140,7 @@ def variants(log=None):
     combinations it cannot run are skipped and logged once."""
     skipped = []
     for p in PLACEMENTS:
-        for b in BPTS:
+        for b in PLAIN_BPTS:
             for w in WGS:
                 if p == aes.AES_PLACEMENT_BITSLICED and (b != 1 or w > BITSLICE_MAX_WG):
                     skipped.append((p, b, w))
@@ -425,6 +427,10 @@ def main(argv=None):
     ap.add_argument("--rounds", type=int, default=3, help="interleaved passes over the variants")
     ap.add_argument("--sizes", default=None,
                     help="comma-separated byte sizes, each tuned on its own (default: two or three per size bucket)")
+    ap.add_argument("--buckets", default=None,
+                    help="comma-separated bucket indices to tune (all key sizes and directions); the results "
+                         "replace those buckets' entries of the record given by --merge")
+    ap.add_argument("--merge", default=None, help="record to update with --buckets (same kernel sources)")
     ap.add_argument("--batch-only", action="store_true",
                     help="tune the batched mix only and store it into the record given by --out (which must exist)")
     ap.add_argument("--emit-defaults", metavar="RECORD", default=None,
@@ -435,6 +441,22 @@ def main(argv=None):
         with open(DEFAULTS_INC, "w") as f:
             f.write(emit_defaults(load(a.emit_defaults)))
         log("wrote", DEFAULTS_INC)
+        return
+    if a.buckets is not None:
+        rec = load(a.merge)
+        if rec.get("source_hash") != source_hash():
+            raise SystemExit("%s was made for kernel sources %s, these are %s: tune everything again" % (
+                a.merge, rec.get("source_hash"), source_hash()))
+        idx = [int(b) for b in a.buckets.split(",") if b]
+        part = run(buckets=tuple(BUCKET_SIZES[b] for b in idx), batch_too=False, reps=a.reps, rounds=a.rounds, log=log)
+        for k in list(rec["plain"]):
+            if aes.aes_size_bucket(max(rec["plain"][k].get("sizes") or [int(k.split("/")[2])]) // 16) in idx:
+                del rec["plain"][k]
+        rec["plain"].update(part["plain"])
+        rec["merged"] = rec.get("merged", []) + [{"buckets": idx, "created": part["created"]}]
+        with open(a.out, "w") as f:
+            json.dump(rec, f, indent=1)
+        log("wrote", a.out)
         return
     if a.batch_only:
         import torch

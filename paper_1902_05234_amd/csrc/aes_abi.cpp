@@ -68,15 +68,17 @@ uint32_t inv_mix_column(uint32_t x)
     return r;
 }
 
-// Size buckets of the tuning table: <=4 KiB, <=64 KiB, <=2 MiB, <=8 MiB, <=32 MiB, larger.
+// Size buckets of the tuning table: <=4 KiB, <=64 KiB, <=512 KiB, <=2 MiB,
+// <=8 MiB, <=32 MiB, larger.
 int size_bucket(uint64_t nblocks)
 {
     if (nblocks <= 256) return 0;
     if (nblocks <= 4096) return 1;
-    if (nblocks <= 131072) return 2;
-    if (nblocks <= 524288) return 3;
-    if (nblocks <= 2097152) return 4;
-    return 5;
+    if (nblocks <= 32768) return 2;
+    if (nblocks <= 131072) return 3;
+    if (nblocks <= 524288) return 4;
+    if (nblocks <= 2097152) return 5;
+    return 6;
 }
 
 struct TuneEntry {

@@ -35,9 +35,9 @@
 // one v_perm_b32 per lookup, and the last round merges its four bytes with
 // two more.  A byte permute issues at about half the rate of a plain
 // v_bitop3_b32, so in instruction slots it costs what the two-instruction
-// shift-and-OR form costs; but the kernel runs at the board power limit,
-// where fewer instructions (and fewer VGPR reads: the selectors stay in
-// SGPRs) mean less energy per block and a higher engine clock.
+// shift-and-OR form costs; but under this load the engine clock drops well
+// below its peak, and fewer instructions (and fewer VGPR reads: the
+// selectors stay in SGPRs) measured a higher clock and a higher rate.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>

@@ -308,8 +308,8 @@ def test_tuning_table_round_trip():
                 got = aes.aes_tune_get(nr, dec, nb)
                 assert (got.bpt, got.wg, got.placement) == (2, 512, aes.AES_PLACEMENT_TTABLE4)
                 aes.aes_tune_set(nr, dec, nb, old)
-    assert [aes.aes_size_bucket(n) for n in (1, 256, 257, 4096, 4097, 131072, 131073, 524288, 524289, 2097152,
-                                             2097153)] == [0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 5]
+    assert [aes.aes_size_bucket(n) for n in (1, 256, 257, 4096, 4097, 32768, 32769, 131072, 131073, 524288, 524289,
+                                             2097152, 2097153)] == [0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 5, 6]
     with pytest.raises(aes.AesError):
         aes.aes_tune_set(10, False, 1, aes.Variant(bpt=8))
     with pytest.raises(aes.AesError):
