@@ -649,8 +649,9 @@ def verify_served(torch, aes, inputs, pool, kt, in_pool, out_arena):
 
 def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=None):
     """Open-loop Poisson arrivals at offered loads rho x peak through the
-    native engine (aes_server_*, 4 streams, 2048-block work items, 64 bytes
-    per thread, 32 GiB budget, 4,096 resident keys): p50/p99 latency
+    native engine (aes_server_*, 4 streams, 2048-block work items and
+    256-block items for requests of at most 2048 blocks, 64 bytes per
+    thread, 32 GiB budget, 4,096 resident keys): p50/p99 latency
     (scheduled arrival -> completion seen by the engine) and sustained GB/s
     per load.  One more
     trace at SATURATION_RHO x peak keeps the queue from ever emptying, so its
@@ -710,6 +711,7 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     best = max(r["GB_s"] for r in rows)
     res = {"engine": "native (aes_server_*)", "peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget,
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
+           "small_item_blocks": 256, "completion": "words written by the streams (hipStreamWriteValue32)",
            "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"],
            "batches": st["batches"], "direct_batches": st["direct_batches"], "levels": rows,
            "max_sustained_GB_s": best, "capacity": capacity, "verified": verified}

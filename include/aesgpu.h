@@ -389,6 +389,14 @@ typedef struct {
     int32_t batch;        /* index of the batch that ran the request */
 } aes_served;
 
+/* AUTO: when the device maps the pinned staging, each slot's stream writes a
+ * completion word into it after the batch kernel (hipStreamWriteValue32) and
+ * the worker reads it with a plain load; otherwise, and with EVENTS, the
+ * worker queries an event recorded after the kernel.  Either way a batch not
+ * seen complete within 2 ms is also checked with the runtime, which reports
+ * a failed kernel (AES_SERVED_FAILED). */
+#define AES_SERVE_COMPLETION_AUTO 0
+#define AES_SERVE_COMPLETION_EVENTS 1
 typedef struct {
     uint64_t budget_bytes;     /* cap on input + output bytes of admitted, unfinished requests */
     uint32_t chunk_blocks;     /* work-item size, 1..AES_MAX_ITEM_BLOCKS */
@@ -399,6 +407,10 @@ typedef struct {
     int32_t dry_run;           /* nonzero: no device work; batches complete after dry_run_seconds */
     double dry_run_seconds;
     int32_t placement;         /* table placement of the batch kernel, as in aes_batch_config */
+    int32_t completion;        /* AES_SERVE_COMPLETION_*: how the worker sees a batch finish */
+    uint32_t small_item_blocks; /* work-item size for requests of at most chunk_blocks blocks, so that
+                                   several waves share a small request (0: chunk_blocks for all);
+                                   at most chunk_blocks */
 } aes_serve_config;
 
 typedef struct {

@@ -452,13 +452,15 @@ SERVED_DTYPE = np.dtype([("id", "<u8"), ("arrival_s", "<f8"), ("admitted_s", "<f
                          ("out_block", "<u8"), ("nblocks", "<u8"), ("status", "<i4"), ("batch", "<i4")])
 assert REQUEST_DTYPE.itemsize == 24 and SERVED_DTYPE.itemsize == 56
 AES_SERVED_DONE, AES_SERVED_REJECTED, AES_SERVED_FAILED = 0, 1, 2
+AES_SERVE_COMPLETION_AUTO, AES_SERVE_COMPLETION_EVENTS = 0, 1
 
 
 class _ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("chunk_blocks", ctypes.c_uint32),
                 ("max_batch_items", ctypes.c_uint32), ("nslots", ctypes.c_int32), ("bpt", ctypes.c_int32),
                 ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("auto_release", ctypes.c_int32),
-                ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double), ("placement", ctypes.c_int32)]
+                ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double), ("placement", ctypes.c_int32),
+                ("completion", ctypes.c_int32), ("small_item_blocks", ctypes.c_uint32)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -504,13 +506,15 @@ class Server:
     def __init__(self, key_table_dev=None, in_pool=None, out_arena=None, *, n_slots=None, in_blocks=None,
                  out_blocks=None, budget_bytes=32 << 30, chunk_blocks=2048, max_batch_items=1 << 18, nslots=4,
                  bpt=4, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0,
-                 placement=AES_PLACEMENT_TTABLE4):
+                 placement=AES_PLACEMENT_TTABLE4, completion=0, small_item_blocks=None):
         lib = _lib()
         _serve_sigs(lib)
         self._lib = lib
         self.cfg = _ServeConfig(int(budget_bytes), int(chunk_blocks), int(max_batch_items), int(nslots), int(bpt),
                                 int(wg), int(grid), int(bool(auto_release)), int(bool(dry_run)), float(dry_run_seconds),
-                                int(placement))
+                                int(placement), int(completion),
+                                # default: one wave unit (64 lanes x bpt blocks) per item of a small request
+                                int(min(64 * bpt, chunk_blocks) if small_item_blocks is None else small_item_blocks))
         ws = lib.aes_server_workspace_bytes(ctypes.byref(self.cfg))
         st = lib.aes_server_staging_bytes(ctypes.byref(self.cfg))
         self._keep = [key_table_dev, in_pool, out_arena]

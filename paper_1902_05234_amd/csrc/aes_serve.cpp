@@ -36,6 +36,9 @@ namespace aesgpu {
 int device_cu_count();
 
 constexpr size_t kDirectItems = 4096;
+// A batch still not seen complete after this long is checked with the runtime
+// (which also reports a failure) on every pass of the worker.
+constexpr double kStreamCheckSeconds = 0.002;
 
 namespace {
 
@@ -97,6 +100,12 @@ private:
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
+    // Completion word in the pinned staging: after the batch kernel the
+    // slot's stream writes `seq` into it (hipStreamWriteValue32), and the
+    // worker sees completion with a plain load instead of an event query.
+    uint32_t* done_word = nullptr;
+    uint32_t seq = 0;
+    double launched = 0;
     aes_work_item* items_dev = nullptr;
     uint32_t* counters_dev = nullptr;
     aes_work_item* staging = nullptr;
@@ -121,6 +130,7 @@ struct aes_server {
     size_t out_blocks = 0;
     std::vector<aesgpu::Slot> slots;
     bool staging_mapped = false;  // kernels may read the work items from the pinned staging
+    bool use_done_word = false;   // completion seen through the slots' completion words
     aesgpu::Arena arena{0};
     aesgpu::Clock::time_point t0;
 
@@ -173,22 +183,33 @@ void finish(aes_server* s, Slot& sl, int status, double t)
 // Work items of a request of n blocks.
 uint64_t items_of(uint64_t n, uint32_t chunk) { return n / chunk + (n % chunk != 0); }
 
+// Work-item size for a request of n blocks : a request of at
+// most chunk_blocks blocks is spread over items of small_item_blocks (when
+// set), so that several waves share it instead of one wave walking it
+// alone; larger requests use chunk_blocks, so that a large request keeps to
+// a few CUs and leaves the others to the batches of other slots.
+uint32_t chunk_for(const aes_serve_config& c, uint64_t n)
+{
+    return (c.small_item_blocks > 0 && n <= c.chunk_blocks) ? c.small_item_blocks : c.chunk_blocks;
+}
+
+uint64_t request_items(const aes_serve_config& c, uint64_t n) { return items_of(n, chunk_for(c, n)); }
+
 bool valid(const aes_server* s, const aes_request& r)
 {
     // the arena bounds come first and the budget is divided, so no product
     // wraps; a request must fit one batch, else it would hold the FIFO forever
     return r.nblocks > 0 && r.nblocks <= s->out_blocks && r.in_block <= s->in_blocks &&
            r.nblocks <= s->in_blocks - r.in_block && r.nblocks <= s->cfg.budget_bytes / 32 &&
-           items_of(r.nblocks, s->cfg.chunk_blocks) <= s->cfg.max_batch_items && r.key_slot < s->n_slots;
+           request_items(s->cfg, r.nblocks) <= s->cfg.max_batch_items && r.key_slot < s->n_slots;
 }
 
 bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
 {
-    const uint32_t chunk = s->cfg.chunk_blocks;
     size_t ne = 0, nd = 0;
     uint64_t enc_b = 0, tot_b = 0;
     for (Req* q : batch) {
-        const uint64_t c = items_of(q->r.nblocks, chunk);
+        const uint64_t c = request_items(s->cfg, q->r.nblocks);
         (q->r.decrypt ? nd : ne) += c;
         tot_b += q->r.nblocks;
         if (!q->r.decrypt)
@@ -196,6 +217,7 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
     }
     size_t ie = 0, id = ne;
     for (Req* q : batch) {
+        const uint32_t chunk = chunk_for(s->cfg, q->r.nblocks);
         const uint64_t c = items_of(q->r.nblocks, chunk);
         for (uint64_t k = 0; k < c; ++k) {
             const uint64_t off = k * chunk;
@@ -229,8 +251,13 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
                     sl.counters_dev, (uint32_t)enc_groups};
         e = launch_batch(a, s->cfg.bpt, s->cfg.placement, grid, s->cfg.wg, sl.stream);
     }
-    if (e == hipSuccess)
-        e = hipEventRecord(sl.event, sl.stream);
+    if (e == hipSuccess) {
+        sl.launched = s->now();
+        if (s->use_done_word)
+            e = hipStreamWriteValue32(sl.stream, sl.done_word, ++sl.seq, 0);
+        else
+            e = hipEventRecord(sl.event, sl.stream);
+    }
     if (e != hipSuccess) {
         s->last_error.store(AES_EHIP);
         finish(s, sl, AES_SERVED_FAILED, s->now());
@@ -297,8 +324,13 @@ void worker_loop(aes_server* s)
             if (s->cfg.dry_run) {
                 if (s->now() >= sl.dry_done)
                     finish(s, sl, AES_SERVED_DONE, s->now());
-            } else {
-                hipError_t q = hipEventQuery(sl.event);
+            } else if (s->use_done_word &&
+                       __atomic_load_n(sl.done_word, __ATOMIC_ACQUIRE) == sl.seq) {
+                finish(s, sl, AES_SERVED_DONE, s->now());
+            } else if (!s->use_done_word || s->now() - sl.launched > kStreamCheckSeconds) {
+                // events, or a batch that has run long: ask the runtime, which
+                // also reports a failed launch or kernel
+                hipError_t q = s->use_done_word ? hipStreamQuery(sl.stream) : hipEventQuery(sl.event);
                 if (q == hipSuccess)
                     finish(s, sl, AES_SERVED_DONE, s->now());
                 else if (q != hipErrorNotReady) {
@@ -323,7 +355,7 @@ void worker_loop(aes_server* s)
                     s->completed.push_back(q);
                     continue;
                 }
-                const uint64_t need = items_of(q->r.nblocks, s->cfg.chunk_blocks);
+                const uint64_t need = request_items(s->cfg, q->r.nblocks);
                 const uint64_t bytes = 2 * 16 * q->r.nblocks;  // valid(): at most the budget
                 if (items + need > s->cfg.max_batch_items || bytes > s->cfg.budget_bytes - s->in_use)
                     break;
@@ -377,6 +409,12 @@ void worker_loop(aes_server* s)
 
 using namespace aesgpu;
 
+// Byte offset of the completion words in the staging (after the work items, 64-byte aligned).
+static size_t staging_words_offset(const aes_serve_config* cfg)
+{
+    return ((size_t)cfg->nslots * cfg->max_batch_items * sizeof(aes_work_item) + 63) & ~(size_t)63;
+}
+
 extern "C" {
 
 size_t aes_server_workspace_bytes(const aes_serve_config* cfg)
@@ -391,7 +429,8 @@ size_t aes_server_staging_bytes(const aes_serve_config* cfg)
 {
     if (cfg == nullptr || cfg->nslots <= 0)
         return 0;
-    return (size_t)cfg->nslots * cfg->max_batch_items * sizeof(aes_work_item);
+    // the slots' work items, then one 64-byte line per slot for its completion word
+    return staging_words_offset(cfg) + (size_t)cfg->nslots * 64;
 }
 
 static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_table_dev, size_t n_slots,
@@ -405,12 +444,13 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
     const aes_serve_config& c = *cfg;
     if (c.nslots < 1 || c.nslots > 16 || c.chunk_blocks == 0 || c.chunk_blocks > AES_MAX_ITEM_BLOCKS ||
         c.max_batch_items == 0 || c.budget_bytes == 0 || (c.bpt != 1 && c.bpt != 2 && c.bpt != 4) || c.wg < 64 ||
-        c.wg > 1024 || c.wg % 64 || c.grid < 0 ||
+        c.wg > 1024 || c.wg % 64 || c.grid < 0 || c.small_item_blocks > c.chunk_blocks ||
+        (c.completion != AES_SERVE_COMPLETION_AUTO && c.completion != AES_SERVE_COMPLETION_EVENTS) ||
         (c.placement != AES_PLACEMENT_TTABLE4 && c.placement != AES_PLACEMENT_TTABLE2 &&
          c.placement != AES_PLACEMENT_TTABLE1))
         return fail(AES_EINVAL, "serve config out of range (nslots 1..16, chunk 1..AES_MAX_ITEM_BLOCKS, "
                                 "items/budget > 0, bpt 1/2/4, wg multiple of 64 in [64, 1024], grid >= 0, "
-                                "placement 0/1/2)");
+                                "placement 0/1/2, completion 0/1, small items at most chunk)");
     if (!c.dry_run && (key_table_dev == nullptr || in_pool == nullptr || out_arena == nullptr ||
                        workspace_dev == nullptr || staging_host == nullptr))
         return fail(AES_EINVAL, "null key table, input pool, output arena, workspace or staging");
@@ -455,6 +495,9 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
         sl.counters_dev = reinterpret_cast<uint32_t*>(base + items_bytes);
         sl.staging = reinterpret_cast<aes_work_item*>(static_cast<char*>(staging_host) +
                                                       (size_t)i * c.max_batch_items * sizeof(aes_work_item));
+        sl.done_word = reinterpret_cast<uint32_t*>(static_cast<char*>(staging_host) + staging_words_offset(cfg) +
+                                                   (size_t)i * 64);
+        __atomic_store_n(sl.done_word, 0u, __ATOMIC_RELEASE);
         if (c.dry_run)
             continue;
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -475,8 +518,10 @@ static int server_create_impl(const aes_serve_config* cfg, const uint32_t* key_t
         delete s;
         return rc;
     }
-    if (!c.dry_run)
+    if (!c.dry_run) {
         s->staging_mapped = host_range_device_mapped(staging_host, aes_server_staging_bytes(cfg));
+        s->use_done_word = s->staging_mapped && c.completion == AES_SERVE_COMPLETION_AUTO;
+    }
     s->t0 = Clock::now();
     try {
         s->worker = std::thread(worker_main, s);

@@ -97,6 +97,25 @@ def test_dry_run_rejects_a_request_larger_than_one_batch():
                                       aes.AES_SERVED_DONE]
 
 
+def test_dry_run_small_requests_are_counted_in_small_items():
+    """A request of at most chunk_blocks blocks is split into items of
+    small_item_blocks: with chunk 256 and small items of 16, a 100-block
+    request needs 7 items and cannot fit a batch of 4, while a 300-block
+    request (two 256-block chunks) fits."""
+    srv = aes.Server(n_slots=2, in_blocks=100000, out_blocks=100000, budget_bytes=1 << 30, chunk_blocks=256,
+                     small_item_blocks=16, max_batch_items=4, nslots=2, dry_run=True, dry_run_seconds=0.0002)
+    r = requests(3, 6, max_blocks=60, pool_blocks=100000, slots=2)
+    r[0]["nblocks"] = 64    # 4 small items: fits
+    r[1]["nblocks"] = 100   # 7 small items: never fits
+    r[2]["nblocks"] = 300   # 2 chunks: fits
+    srv.submit(r)
+    out = wait_all(srv, 3, timeout=10.0)
+    srv.close()
+    assert out["status"].tolist() == [aes.AES_SERVED_DONE, aes.AES_SERVED_REJECTED, aes.AES_SERVED_DONE]
+    with pytest.raises(aes.AesError):
+        aes.Server(n_slots=1, in_blocks=10, out_blocks=10, chunk_blocks=64, small_item_blocks=65, dry_run=True)
+
+
 def test_dry_run_release_frees_only_outputs_still_held():
     """A second release of the same outputs, or a range the engine never
     handed out, is refused (AES_EINVAL) and leaves the arena intact."""
@@ -193,7 +212,8 @@ def test_dry_run_close_with_held_outputs_and_a_blocked_request():
 
 def test_create_rejects_bad_configs():
     for kw in (dict(nslots=0), dict(nslots=17), dict(chunk_blocks=0), dict(chunk_blocks=aes.AES_MAX_ITEM_BLOCKS + 1),
-               dict(bpt=3), dict(wg=100), dict(budget_bytes=0), dict(max_batch_items=0)):
+               dict(bpt=3), dict(wg=100), dict(budget_bytes=0), dict(max_batch_items=0), dict(grid=-1),
+               dict(placement=3), dict(completion=2)):
         args = dict(n_slots=1, in_blocks=10, out_blocks=10, dry_run=True)
         args.update(kw)
         with pytest.raises(aes.AesError):
@@ -202,7 +222,13 @@ def test_create_rejects_bad_configs():
 
 # ------------------------------------------------------------------ GPU part
 @pytest.mark.gpu
-def test_native_served_results_equal_the_request_alone(oracle_lib):
+@pytest.mark.parametrize("completion,placement", [(aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE4),
+                                                  (aes.AES_SERVE_COMPLETION_EVENTS, aes.AES_PLACEMENT_TTABLE4),
+                                                  (aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE2)])
+def test_native_served_results_equal_the_request_alone(oracle_lib, completion, placement):
+    """Every served request equals the request run alone (and the oracle on
+    samples), whichever way the worker sees batches finish (completion words
+    written by the streams, or events) and with the 2-table batch kernel."""
     import torch
     from paper_1902_05234_amd import batch
     pool = inputs.key_pool(6, 32)
@@ -210,7 +236,7 @@ def test_native_served_results_equal_the_request_alone(oracle_lib):
     in_pool = inputs.device_random_bytes(6, 64 << 20)
     out_arena = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda")
     srv = aes.Server(kt, in_pool, out_arena, budget_bytes=512 << 20, chunk_blocks=256, max_batch_items=1 << 14,
-                     nslots=4, auto_release=False)
+                     nslots=4, auto_release=False, completion=completion, placement=placement)
     r = requests(500, 4, max_blocks=20000, pool_blocks=in_pool.numel() // 16, slots=len(pool))
     srv.submit(r[:250])
     time.sleep(0.001)
