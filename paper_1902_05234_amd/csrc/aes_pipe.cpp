@@ -114,10 +114,12 @@ hipError_t launch_piece(int op, int nr, const RoundKeys& keys, const Counter128&
     aes_variant v;
     aes_tune_get(nr, op == AES_PIPE_ECB_DECRYPT ? 1 : 0, blocks, &v);
     if (op == AES_PIPE_CTR && v.placement == AES_PLACEMENT_BITSLICED) {
-        v.placement = AES_PLACEMENT_TTABLE2;  // CTR runs on the table placements
+        v.placement = AES_PLACEMENT_TTABLE2;  // CTR runs on the whole-state table kernels
         v.bpt = 2;
         v.wg = 1024;
     }
+    if (op == AES_PIPE_CTR && v.bpt == AES_BPT_COLUMN)
+        v.bpt = 1;  // the one-column-per-lane variant is ECB only
     const LaunchShape shape{v.bpt, v.wg, 0};
     if (op == AES_PIPE_CTR) {
         Counter128 c = c0;
