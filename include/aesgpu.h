@@ -335,8 +335,12 @@ int aes_ecb_batch(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, co
  * skipped as in aes_ecb_batch but their count is not reported.  Every call on
  * one device shares that device's scratch: calls whose launches overlap in
  * time on one device (different streams, or graphs replayed concurrently)
- * race on the counters and must not be issued.  AES_EHIP if the scratch's
- * device address cannot be obtained or a launch fails.
+ * race on the counters and must not be issued.  The first call on each
+ * device looks up the scratch's device address (hipGetSymbolAddress) and the
+ * chosen variant's occupancy: a caller that captures the launch in a HIP
+ * graph makes one call on that device, with that configuration, before it
+ * begins the capture.  AES_EHIP if the scratch's device address cannot be
+ * obtained or a launch fails.
  */
 #define AES_NOALLOC_SCRATCH_BYTES 256
 int aes_ecb_batch_noalloc(const aes_work_item *items_dev, size_t n_enc, size_t n_dec, const uint32_t *key_table_dev,

@@ -19,7 +19,7 @@ def test_plain_paths_replay_in_a_graph(oracle_lib):
     n = 16 * 70001
     x = inputs.random_bytes(952, n)
     xd = to_dev(x)
-    outs = {name: torch.empty_like(xd) for name in ("enc4", "enc2", "enc1", "encb", "dec", "ctr", "cbc")}
+    outs = {name: torch.empty_like(xd) for name in ("enc4", "enc2", "enc1", "encb", "encc", "dec", "ctr", "cbc")}
     cd = to_dev(oracle_lib.ecb_encrypt(key, x))
     cbc_in = to_dev(oracle_lib.cbc_encrypt(key, iv, x))
 
@@ -28,6 +28,8 @@ def test_plain_paths_replay_in_a_graph(oracle_lib):
         aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, xd, outs["enc2"], aes.Variant(bpt=2, wg=1024, placement=1))
         aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, xd, outs["enc1"], aes.Variant(bpt=1, wg=512, placement=2))
         aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, xd, outs["encb"], aes.Variant(bpt=1, wg=256, placement=3))
+        aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, xd, outs["encc"],
+                                  aes.Variant(bpt=aes.AES_BPT_COLUMN, wg=512, placement=1))
         aes.aes_ecb_decrypt(ks.rk_dec, ks.nr, cd, outs["dec"])
         aes.aes_ctr_crypt(ks.rk_enc, ks.nr, iv, 5, xd, outs["ctr"])
         aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, iv, cbc_in, outs["cbc"])
@@ -36,7 +38,7 @@ def test_plain_paths_replay_in_a_graph(oracle_lib):
     torch.cuda.synchronize()
     eager = {k: to_host(v).copy() for k, v in outs.items()}
     want_enc = oracle_lib.ecb_encrypt(key, x)
-    for k in ("enc4", "enc2", "enc1", "encb"):
+    for k in ("enc4", "enc2", "enc1", "encb", "encc"):
         assert first_mismatch(eager[k], want_enc) is None, k
     assert first_mismatch(eager["dec"], x) is None
     assert first_mismatch(eager["ctr"], oracle_lib.ctr_crypt(key, iv, x, offset=5)) is None

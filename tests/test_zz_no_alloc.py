@@ -65,3 +65,38 @@ def test_noalloc_batch_rejects_what_aes_ecb_batch_rejects():
                                   aes.BatchConfig(bpt=3))
     with pytest.raises(aes.AesError):
         aes.aes_ecb_batch_noalloc(b.items_dev, b.n_enc, b.n_dec, b.key_table_dev, b.in_arena[16:], b.in_arena[:-16])
+
+
+def test_noalloc_batch_replays_in_a_graph():
+    """The callers this entry point is for capture it: a graph holding the
+    counter-zeroing kernel and the batch kernel, replayed four times with
+    eager work (an aes_ecb_batch launch that uses its own counters) and
+    synchronisations between the replays, equals the eager output each time."""
+    torch = cuda()
+    b = _batch(torch, 72, 150, 256 << 10, 512, aes.BatchConfig(bpt=4, wg=1024))
+    b.launch()
+    torch.cuda.synchronize()
+    want = b.out_arena.clone()
+    # one call outside the capture: the first call on a device looks up the
+    # scratch's address and the variant's occupancy, which a capture forbids
+    aes.aes_ecb_batch_noalloc(b.items_dev, b.n_enc, b.n_dec, b.key_table_dev, b.in_arena, b.out_arena, b.cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(b.out_arena, want)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            aes.aes_ecb_batch_noalloc(b.items_dev, b.n_enc, b.n_dec, b.key_table_dev, b.in_arena, b.out_arena,
+                                      b.cfg)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        b.out_arena.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(b.out_arena, want), "replay %d differs from aes_ecb_batch" % rep
+        b.launch()  # eager work between replays
+        torch.cuda.synchronize()
+    del g
