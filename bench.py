@@ -842,13 +842,15 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host-inclusive file-size sweep")
     ap.add_argument("--serve-levels", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9,1.0")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid", "corun", "corun-sweep", "ctr"),
+    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid", "corun", "corun-sweep", "ctr", "variants", "host"),
                     default=None,
                     help="bulk: only a few copy and 1 GiB launches; mid: graph-replayed AES-128 encryptions of "
                          "64 KiB ... 32 MiB and of a 16-byte copy (for rocprofv3 kernel traces); corun: the "
                          "bitsliced kernel beside the 4-table kernel on two streams, 30 steps (for a kernel "
                          "trace); corun-sweep: their sustained rates over bitsliced shares 0 ... 0.24; ctr: 1 GiB CTR and ECB "
-                         "encryptions in turn (for counters)")
+                         "encryptions in turn (for counters); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
+                         "and the bitsliced kernel at 1 GiB (for counters); host: the host-inclusive file-size sweep "
+                         "only (for a kernel and copy trace)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -872,6 +874,25 @@ def main():
         return
     if args.profile in ("corun", "corun-sweep"):
         corun(torch, aes, inputs, args.profile == "corun-sweep")
+        return
+    if args.profile == "variants":
+        # the tuned defaults below 32 MiB and the bitsliced kernel, three launches
+        # each (for counters of the kernels that serve small and mid sizes)
+        x = inputs.device_random_bytes(1, GiB)
+        y = torch.empty_like(x)
+        ks = aes.aes_expand_key(inputs.random_key(1, 128))
+        for n in (256 << 10, 4 * MiB, 16 * MiB):
+            log("variant at %d bytes:" % n, aes.aes_tune_get(10, False, n // 16))
+            for _ in range(3):
+                aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x[:n], y[:n])
+        vb = aes.Variant(bpt=1, wg=256, placement=aes.AES_PLACEMENT_BITSLICED)
+        for _ in range(3):
+            aes.aes_ecb_crypt_variant(ks.rk_enc, ks.nr, False, x, y, vb)
+        torch.cuda.synchronize()
+        log("variant profile launches done")
+        return
+    if args.profile == "host":
+        log(json.dumps(host_sweep(torch, aes, inputs, reps=5)))
         return
     if args.profile == "ctr":
         # counter mode beside ECB encryption, 1 GiB each, tuned defaults (for
