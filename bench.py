@@ -713,7 +713,8 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
            "small_item_blocks": 256, "completion": "words written by the streams (hipStreamWriteValue32)",
            "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"],
-           "batches": st["batches"], "direct_batches": st["direct_batches"], "levels": rows,
+           "batches": st["batches"], "direct_batches": st["direct_batches"],
+           "launch_us_per_batch": round(st["launch_ns"] / 1e3 / max(1, st["batches"]), 2), "levels": rows,
            "max_sustained_GB_s": best, "capacity": capacity, "verified": verified}
     if bulk_equivalent_gbps:
         res["max_sustained_vs_bulk"] = round(best / bulk_equivalent_gbps, 4)

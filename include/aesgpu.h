@@ -424,6 +424,8 @@ typedef struct {
     uint64_t pending;
     uint64_t direct_batches; /* batches whose kernel read the work list from the pinned staging
                                 (device-mapped staging, at most 4096 items: no copy) */
+    uint64_t launch_ns;      /* worker time spent in the runtime calls that launch batches
+                                (work-list copy, kernel, completion word or event), all batches */
 } aes_serve_stats;
 
 typedef struct aes_server aes_server;

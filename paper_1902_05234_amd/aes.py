@@ -466,7 +466,7 @@ class _ServeConfig(ctypes.Structure):
 class _ServeStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("max_device_bytes_in_use", ctypes.c_uint64),
                 ("arena_blocks_in_use", ctypes.c_uint64), ("pending", ctypes.c_uint64),
-                ("direct_batches", ctypes.c_uint64)]
+                ("direct_batches", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64)]
 
 
 def _serve_sigs(lib):
@@ -565,7 +565,7 @@ class Server:
         _check_rc(self._lib.aes_server_stats(self._h, ctypes.byref(s)), "aes_server_stats")
         return {"batches": s.batches, "max_device_bytes_in_use": s.max_device_bytes_in_use,
                 "arena_blocks_in_use": s.arena_blocks_in_use, "pending": s.pending,
-                "direct_batches": s.direct_batches}
+                "direct_batches": s.direct_batches, "launch_ns": s.launch_ns}
 
     def replay(self, reqs, arrival_s) -> np.ndarray:
         reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)

@@ -148,6 +148,7 @@ struct aes_server {
     uint64_t in_use = 0;
     std::atomic<uint64_t> batches{0};      // written by the worker, read by aes_server_stats
     std::atomic<uint64_t> direct_batches{0};
+    std::atomic<uint64_t> launch_ns{0};    // worker time inside the launch calls of all batches
     std::atomic<uint64_t> max_in_use{0};
     std::atomic<int> last_error{AES_OK};
     std::atomic<bool> broken{false};       // the worker stopped on an internal failure
@@ -236,6 +237,7 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
         return true;
     }
     const size_t n = ne + nd;
+    const auto t_launch = Clock::now();
     const bool direct = s->staging_mapped && n <= kDirectItems;
     if (direct)
         s->direct_batches.fetch_add(1, std::memory_order_relaxed);
@@ -258,6 +260,9 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
         else
             e = hipEventRecord(sl.event, sl.stream);
     }
+    s->launch_ns.fetch_add(
+        (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t_launch).count(),
+        std::memory_order_relaxed);
     if (e != hipSuccess) {
         s->last_error.store(AES_EHIP);
         finish(s, sl, AES_SERVED_FAILED, s->now());
@@ -644,6 +649,7 @@ static int server_stats_impl(aes_server* s, aes_serve_stats* st)
     st->arena_blocks_in_use = s->arena_used_pub.load(std::memory_order_relaxed);
     st->pending = s->pending_pub.load(std::memory_order_relaxed) + s->incoming.size();
     st->direct_batches = s->direct_batches.load(std::memory_order_relaxed);
+    st->launch_ns = s->launch_ns.load(std::memory_order_relaxed);
     return AES_OK;
 }
 

@@ -291,6 +291,7 @@ def test_native_light_batches_read_items_from_pinned_staging(oracle_lib):
     st = srv.stats()
     assert st["batches"] >= 8
     assert st["direct_batches"] == st["batches"], "every batch here fits the direct work-list path"
+    assert 0 < st["launch_ns"] < 1_000_000 * st["batches"], "launch time is counted and under 1 ms a batch"
     scheds = [aes.aes_expand_key(k) for _, k in pool]
     for i, q in enumerate(r):
         ks = scheds[int(q["key_slot"])]
