@@ -32,10 +32,10 @@ library's defaults are the record's winners.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -58,15 +58,39 @@ RECORD = os.path.join(HERE, "tuning", "mi355x_sweep.json")
 DEFAULTS_INC = os.path.join(HERE, "csrc", "aes_tune_defaults.inc")
 
 
+# Kernels whose timings a record holds: the plain ECB kernels (every table
+# placement, one column per lane, bitsliced) with their dispatcher, and the
+# batched kernel.  The record's source hash covers these files and the csrc
+# headers they include, followed transitively; other device code (CTR, CBC,
+# probes), host code and the public header do not change those timings.
+TUNED_KERNELS = ("aes_ecb.hip", "aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip", "aes_ecb_col.hip",
+                 "aes_bitslice.hip", "aes_batch.hip")
+
+
+def tuned_sources() -> list:
+    """TUNED_KERNELS and every csrc header they include (transitively)."""
+    csrc = os.path.join(HERE, "csrc")
+    seen, todo = set(), list(TUNED_KERNELS)
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        for m in re.finditer(r'^\s*#\s*include\s+"([^"/]+)"', text, re.M):
+            if os.path.exists(os.path.join(csrc, m.group(1))):
+                todo.append(m.group(1))
+    return sorted(seen)
+
+
 def source_hash() -> str:
-    """Hash of the device code the timings depend on (the .hip and .hpp
-    sources; host-only files, the generated default table and caches are
-    left out)."""
+    """Hash of the device code the recorded timings depend on (tuned_sources)."""
     h = hashlib.sha256()
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+    for f in tuned_sources():
+        h.update(f.encode())
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -35,12 +35,21 @@ def test_bucket_winner_ignores_variants_missing_at_some_size():
     assert (w["bpt"], w["wg"], w["placement"]) == (1, 512, 2)
 
 
-def test_source_hash_covers_device_sources_only():
-    """The record's source hash reads the .hip/.hpp files and ignores
-    anything else under csrc (a __pycache__ directory, host-only sources)."""
+def test_source_hash_covers_the_tuned_kernels_and_their_headers():
+    """The record's source hash reads the tuned kernels and every csrc header
+    they include, and nothing else: device code the record does not time
+    (CTR, CBC, probes) can change without voiding it."""
     import os
+    import re
     from paper_1902_05234_amd import autotune
     csrc = os.path.join(os.path.dirname(autotune.__file__), "csrc")
+    files = autotune.tuned_sources()
+    assert set(autotune.TUNED_KERNELS) <= set(files)
+    for f in files:  # closed under local includes
+        for inc in re.findall(r'^\s*#\s*include\s+"([^"/]+)"', open(os.path.join(csrc, f)).read(), re.M):
+            assert inc in files, (f, inc)
+    for other in ("aes_ctr.hip", "aes_cbc.hip", "aes_microbench.hip", "aes_abi.cpp", "aes_serve.cpp"):
+        assert other not in files
     os.makedirs(os.path.join(csrc, "__pycache__"), exist_ok=True)
     h = autotune.source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
