@@ -59,18 +59,21 @@ DEFAULTS_INC = os.path.join(HERE, "csrc", "aes_tune_defaults.inc")
 
 
 # Kernels whose timings a record holds: the plain ECB kernels (every table
-# placement, one column per lane, bitsliced) with their dispatcher, and the
-# batched kernel.  The record's source hash covers these files and the csrc
-# headers they include, followed transitively; other device code (CTR, CBC,
-# probes), host code and the public header do not change those timings.
-TUNED_KERNELS = ("aes_ecb.hip", "aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip", "aes_ecb_col.hip",
-                 "aes_bitslice.hip", "aes_batch.hip")
+# placement, one column per lane, bitsliced) with their dispatcher, and,
+# tuned apart, the batched kernel.  The record's source hash covers the plain
+# kernels' files and the csrc headers they include, followed transitively;
+# its batch entry carries the same hash of the batched kernel's files.  Other
+# device code (CTR, CBC, probes), host code and the public header do not
+# change those timings.
+PLAIN_KERNELS = ("aes_ecb.hip", "aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip", "aes_ecb_col.hip",
+                 "aes_bitslice.hip")
+BATCH_KERNELS = ("aes_batch.hip",)
 
 
-def tuned_sources() -> list:
-    """TUNED_KERNELS and every csrc header they include (transitively)."""
+def tuned_sources(kernels=PLAIN_KERNELS) -> list:
+    """``kernels`` and every csrc header they include (transitively)."""
     csrc = os.path.join(HERE, "csrc")
-    seen, todo = set(), list(TUNED_KERNELS)
+    seen, todo = set(), list(kernels)
     while todo:
         f = todo.pop()
         if f in seen:
@@ -84,10 +87,11 @@ def tuned_sources() -> list:
     return sorted(seen)
 
 
-def source_hash() -> str:
-    """Hash of the device code the recorded timings depend on (tuned_sources)."""
+def source_hash(kernels=PLAIN_KERNELS) -> str:
+    """Hash of the device code that timings of ``kernels`` depend on
+    (tuned_sources); the default is the plain kernels'."""
     h = hashlib.sha256()
-    for f in tuned_sources():
+    for f in tuned_sources(kernels):
         h.update(f.encode())
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -281,11 +285,14 @@ def tune_batch(torch, n_messages: int = 20000, reps: int = 3, rounds: int = 2, l
         if b.rejected_items() or not torch.equal(out_arena, ref):
             raise RuntimeError("batch chunk=%d %s differs from the per-message plain launches" % (chunk, cfg))
         prepared.append(b)
+        if len(prepared) % 12 == 0:
+            log("  batch variants checked: %d of %d" % (len(prepared), len(vs)))
     del ref
     times = {i: [] for i in range(len(vs))}
-    for _ in range(max(1, rounds)):
+    for r in range(max(1, rounds)):
         for i, b in enumerate(prepared):
             times[i] += _times(torch, b.launch, reps)
+        log("  batch timing pass %d of %d done" % (r + 1, max(1, rounds)))
     rows = []
     for i, (chunk, cfg) in enumerate(vs):
         t = sorted(times[i])
@@ -297,14 +304,16 @@ def tune_batch(torch, n_messages: int = 20000, reps: int = 3, rounds: int = 2, l
         log("  batch chunk=%d bpt=%d wg=%d placement=%d: %.1f GB/s" % (
             r["chunk_blocks"], r["bpt"], r["wg"], r["placement"], r["GB_s"]))
     w = rows[0]
-    return {"winner": {k: w[k] for k in ("chunk_blocks", "bpt", "wg", "placement")}, "GB_s": round(w["GB_s"], 1),
+    return {"source_hash": source_hash(BATCH_KERNELS), "created": time.strftime("%Y-%m-%dT%H:%M:%S"),
+            "winner": {k: w[k] for k in ("chunk_blocks", "bpt", "wg", "placement")}, "GB_s": round(w["GB_s"], 1),
             "messages": n_messages, "bytes": prepared[0].total_bytes, "all": rows}
 
 
 def batch_winner(record: dict):
-    """(chunk_blocks, BatchConfig) of a record's batched winner, or None."""
+    """(chunk_blocks, BatchConfig) of a record's batched winner, or None when
+    the record has none or timed other batch-kernel sources."""
     b = record.get("batch")
-    if not isinstance(b, dict) or "winner" not in b:
+    if not isinstance(b, dict) or "winner" not in b or b.get("source_hash") != source_hash(BATCH_KERNELS):
         return None
     w = b["winner"]
     return w["chunk_blocks"], aes.BatchConfig(bpt=w["bpt"], wg=w["wg"], placement=w["placement"])
@@ -485,6 +494,10 @@ def main(argv=None):
     if a.batch_only:
         import torch
         rec = load(a.out)
+        name, arch = device_identity(torch)
+        if (rec.get("device"), rec.get("arch")) != (name, arch):
+            raise SystemExit("%s was made on %s (%s), this is %s (%s): tune everything again" % (
+                a.out, rec.get("device"), rec.get("arch"), name, arch))
         rec["batch"] = tune_batch(torch, log=log)
         with open(a.out, "w") as f:
             json.dump(rec, f, indent=1)

@@ -44,9 +44,10 @@ __device__ __forceinline__ void run_item(const uint4* __restrict__ in, uint4* __
     for (int i = 0; i < 4 * (NR + 1); ++i) {
         k[i] = __builtin_amdgcn_readfirstlane(kp[i]);
         // the 2-table round takes inner-round key words turned right by 8
-        // bits (see crypt_rounds); uniform values, so scalar work
+        // bits (see crypt_rounds); taken back to a scalar register, else the
+        // turned words stay in VGPRs and the 64-VGPR build spills
         if (PL == kPlace2 && i >= 4 && i < 4 * NR)
-            k[i] = (k[i] >> 8) | (k[i] << 24);
+            k[i] = __builtin_amdgcn_readfirstlane((k[i] >> 8) | (k[i] << 24));
     }
     auto key = [&](int i) { return k[i]; };
     const uint32_t lane = threadIdx.x & 63u;

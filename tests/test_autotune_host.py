@@ -35,22 +35,26 @@ def test_bucket_winner_ignores_variants_missing_at_some_size():
     assert (w["bpt"], w["wg"], w["placement"]) == (1, 512, 2)
 
 
-def test_source_hash_covers_the_tuned_kernels_and_their_headers():
-    """The record's source hash reads the tuned kernels and every csrc header
-    they include, and nothing else: device code the record does not time
-    (CTR, CBC, probes) can change without voiding it."""
+def test_source_hashes_cover_the_tuned_kernels_and_their_headers():
+    """The record's plain hash reads the plain kernels and every csrc header
+    they include, its batch hash the batched kernel's, and nothing else:
+    device code the record does not time (CTR, CBC, probes) can change
+    without voiding it, and the batched kernel can change without voiding
+    the plain timings."""
     import os
     import re
     from paper_1902_05234_amd import autotune
     csrc = os.path.join(os.path.dirname(autotune.__file__), "csrc")
-    files = autotune.tuned_sources()
-    assert set(autotune.TUNED_KERNELS) <= set(files)
-    for f in files:  # closed under local includes
-        for inc in re.findall(r'^\s*#\s*include\s+"([^"/]+)"', open(os.path.join(csrc, f)).read(), re.M):
-            assert inc in files, (f, inc)
-    for other in ("aes_ctr.hip", "aes_cbc.hip", "aes_microbench.hip", "aes_abi.cpp", "aes_serve.cpp"):
-        assert other not in files
+    for kernels in (autotune.PLAIN_KERNELS, autotune.BATCH_KERNELS):
+        files = autotune.tuned_sources(kernels)
+        assert set(kernels) <= set(files)
+        for f in files:  # closed under local includes
+            for inc in re.findall(r'^\s*#\s*include\s+"([^"/]+)"', open(os.path.join(csrc, f)).read(), re.M):
+                assert inc in files, (f, inc)
+        for other in ("aes_ctr.hip", "aes_cbc.hip", "aes_microbench.hip", "aes_abi.cpp", "aes_serve.cpp"):
+            assert other not in files
+    assert "aes_batch.hip" not in autotune.tuned_sources()
     os.makedirs(os.path.join(csrc, "__pycache__"), exist_ok=True)
     h = autotune.source_hash()
-    assert len(h) == 16 and int(h, 16) >= 0
+    assert len(h) == 16 and int(h, 16) >= 0 and h != autotune.source_hash(autotune.BATCH_KERNELS)
     assert autotune.source_hash() == h

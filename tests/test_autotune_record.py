@@ -16,6 +16,8 @@ def test_record_is_for_the_current_kernel_sources():
     rec = _record()
     assert rec["source_hash"] == autotune.source_hash(), (
         "the kernel sources changed since the record was made: re-run the autotuner on an MI355X")
+    assert rec["batch"]["source_hash"] == autotune.source_hash(autotune.BATCH_KERNELS), (
+        "the batched kernel changed since its entry was timed: re-run the autotuner with --batch-only")
     assert rec.get("arch", "").startswith("gfx950")
 
 
@@ -46,6 +48,8 @@ def test_largest_bucket_winner_was_timed_under_sustained_load():
 def test_record_has_a_batch_winner_from_the_full_search():
     rec = _record()
     chunk, cfg = autotune.batch_winner(rec)
+    stale = dict(rec, batch=dict(rec["batch"], source_hash="0000000000000000"))
+    assert autotune.batch_winner(stale) is None, "a batch entry timed on other sources is not used"
     assert chunk in autotune.BATCH_CHUNKS and cfg.placement in autotune.BATCH_PLACEMENTS
     seen = {(r["chunk_blocks"], r["bpt"], r["wg"], r["placement"]) for r in rec["batch"]["all"]}
     assert seen == {(c, v.bpt, v.wg, v.placement) for c, v in autotune.batch_variants()}
