@@ -715,7 +715,7 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     best = max(r["GB_s"] for r in rows)
     res = {"engine": "native (aes_server_*)", "peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget,
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
-           "small_item_blocks": 256, "completion": "words written by the streams (hipStreamWriteValue32)",
+           "small_item_blocks": 256, "completion": "words written by the batch kernel's last workgroup",
            "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"],
            "batches": st["batches"], "direct_batches": st["direct_batches"],
            "launch_us_per_batch": round(st["launch_ns"] / 1e3 / max(1, st["batches"]), 2), "levels": rows,

@@ -393,9 +393,9 @@ typedef struct {
     int32_t batch;        /* index of the batch that ran the request */
 } aes_served;
 
-/* AUTO: when the device maps the pinned staging, each slot's stream writes a
- * completion word into it after the batch kernel (hipStreamWriteValue32) and
- * the worker reads it with a plain load; otherwise, and with EVENTS, the
+/* AUTO: when the device maps the pinned staging, the batch kernel's last
+ * workgroup writes a completion word into it (after every workgroup's output
+ * stores) and the worker reads it with a plain load; otherwise, and with EVENTS, the
  * worker queries an event recorded after the kernel.  Either way a batch not
  * seen complete within 2 ms is also checked with the runtime, which reports
  * a failed kernel (AES_SERVED_FAILED). */

@@ -19,13 +19,15 @@
 //
 // Every item is checked against the arena sizes, the key-table size and the
 // largest item size before use; a bad item is skipped and counted in
-// counters[3].
+// counters[3].  For the serving engine the last workgroup also writes a
+// completion word in host memory (launch_batch_signal).
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <mutex>
 
+#include "aes_batch_signal.hpp"
 #include "aes_device.hpp"
 #include "aes_internal.hpp"
 
@@ -126,7 +128,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PL == kPla
                                                      uint32_t n_dec, const uint32_t* __restrict__ key_table,
                                                      uint32_t n_slots, const uint4* __restrict__ in_base,
                                                      uint4* __restrict__ out_base, uint64_t in_blocks,
-                                                     uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups)
+                                                     uint64_t out_blocks, uint32_t* counters, uint32_t enc_groups,
+                                                     uint32_t* done_word, uint32_t done_seq)
 {
     __shared__ __align__(16) uint32_t lds[Layout<PL, true>::words];  // the larger of the two directions
     bool dec = blockIdx.x >= enc_groups;
@@ -153,6 +156,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PL == kPla
             atomicExch(&counters[1], 0u);
             atomicExch(&counters[2], 0u);
             __threadfence();
+            // every workgroup released its stores before counting itself
+            if (done_word != nullptr)
+                __hip_atomic_store(done_word, done_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
@@ -234,12 +240,15 @@ hipError_t batch_groups_per_cu(int bpt, int placement, int wg, int* per_cu)
     return hipSuccess;
 }
 
-hipError_t launch_batch(const BatchArgs& a, int bpt, int placement, int grid, int wg, hipStream_t stream)
+namespace {
+
+hipError_t launch_batch_impl(const BatchArgs& a, int bpt, int placement, int grid, int wg, uint32_t* done_word,
+                             uint32_t seq, hipStream_t stream)
 {
 #define AESGPU_BATCH_LAUNCH(B, P)                                                                                  \
     hipLaunchKernelGGL((batch_kernel<B, P>), dim3(grid), dim3(wg), 0, stream, a.items, a.n_enc, a.n_dec,           \
                        a.key_table, a.n_slots, static_cast<const uint4*>(a.in_base), static_cast<uint4*>(a.out_base), \
-                       a.in_blocks, a.out_blocks, a.counters, a.enc_groups)
+                       a.in_blocks, a.out_blocks, a.counters, a.enc_groups, done_word, seq)
 #define AESGPU_BATCH_PLACEMENT(P)                   \
     switch (bpt) {                                  \
     case 1: AESGPU_BATCH_LAUNCH(1, P); break;       \
@@ -256,6 +265,21 @@ hipError_t launch_batch(const BatchArgs& a, int bpt, int placement, int grid, in
 #undef AESGPU_BATCH_PLACEMENT
 #undef AESGPU_BATCH_LAUNCH
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs& a, int bpt, int placement, int grid, int wg, hipStream_t stream)
+{
+    return launch_batch_impl(a, bpt, placement, grid, wg, nullptr, 0u, stream);
+}
+
+hipError_t launch_batch_signal(const BatchArgs& a, int bpt, int placement, int grid, int wg, uint32_t* done_word,
+                               uint32_t seq, hipStream_t stream)
+{
+    if (done_word == nullptr)
+        return hipErrorInvalidValue;
+    return launch_batch_impl(a, bpt, placement, grid, wg, done_word, seq, stream);
 }
 
 // Claim counters of the allocation-free batched launch

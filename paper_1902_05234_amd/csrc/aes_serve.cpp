@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "../../include/aesgpu.h"
+#include "aes_batch_signal.hpp"
 #include "aes_internal.hpp"
 
 namespace aesgpu {
@@ -100,9 +101,9 @@ private:
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
-    // Completion word in the pinned staging: after the batch kernel the
-    // slot's stream writes `seq` into it (hipStreamWriteValue32), and the
-    // worker sees completion with a plain load instead of an event query.
+    // Completion word in the pinned staging: the batch kernel's last
+    // workgroup writes `seq` into it (launch_batch_signal), and the worker
+    // sees completion with a plain load instead of an event query.
     uint32_t* done_word = nullptr;
     uint32_t seq = 0;
     double launched = 0;
@@ -251,12 +252,16 @@ bool launch(aes_server* s, Slot& sl, std::vector<Req*>& batch)
         BatchArgs a{static_cast<const WorkItem*>(items), (uint32_t)ne, (uint32_t)nd, s->key_table,
                     (uint32_t)s->n_slots, s->in_pool, s->out_arena, (uint64_t)s->in_blocks, (uint64_t)s->out_blocks,
                     sl.counters_dev, (uint32_t)enc_groups};
-        e = launch_batch(a, s->cfg.bpt, s->cfg.placement, grid, s->cfg.wg, sl.stream);
+        // with completion words the kernel's last workgroup writes the word
+        e = s->use_done_word
+                ? launch_batch_signal(a, s->cfg.bpt, s->cfg.placement, grid, s->cfg.wg, sl.done_word, sl.seq + 1,
+                                      sl.stream)
+                : launch_batch(a, s->cfg.bpt, s->cfg.placement, grid, s->cfg.wg, sl.stream);
     }
     if (e == hipSuccess) {
         sl.launched = s->now();
         if (s->use_done_word)
-            e = hipStreamWriteValue32(sl.stream, sl.done_word, ++sl.seq, 0);
+            ++sl.seq;
         else
             e = hipEventRecord(sl.event, sl.stream);
     }

@@ -5,6 +5,7 @@
 // the tests that run against that build never reach the device.
 #include <hip/hip_runtime.h>
 
+#include "aes_batch_signal.hpp"
 #include "aes_internal.hpp"
 
 namespace aesgpu {
@@ -38,6 +39,11 @@ hipError_t launch_cbc_decrypt(const LaunchShape&, int, int, const void*, void*, 
 }
 
 hipError_t launch_batch(const BatchArgs&, int, int, int, int, hipStream_t) { return hipErrorInvalidValue; }
+
+hipError_t launch_batch_signal(const BatchArgs&, int, int, int, int, uint32_t*, uint32_t, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
 
 hipError_t batch_groups_per_cu(int, int, int, int*) { return hipErrorInvalidValue; }
 
