@@ -670,7 +670,7 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     budget = 32 * GiB
     out_arena = torch.empty(budget // 2, dtype=torch.uint8, device="cuda")
     srv = aes.Server(kt, in_pool, out_arena, budget_bytes=budget, chunk_blocks=2048, max_batch_items=1 << 18,
-                     nslots=4, bpt=4, auto_release=True)
+                     nslots=4, bpt=4, auto_release=True, size_classes=True)
     mean_b = inputs.mean_trace_bytes()
     rows = []
     pool_blocks = pool_bytes // 16
@@ -716,6 +716,7 @@ def serving(torch, aes, inputs, peak_gbps, levels, n_req, bulk_equivalent_gbps=N
     res = {"engine": "native (aes_server_*)", "peak_GB_s": round(peak_gbps, 1), "budget_bytes": budget,
            "key_pool": len(pool), "mean_request_bytes": round(mean_b), "streams": 4, "chunk_blocks": 2048, "bpt": 4,
            "small_item_blocks": 256, "completion": "words written by the batch kernel's last workgroup",
+           "size_classes": True,
            "requests_per_level": n_req, "max_device_bytes_in_use": st["max_device_bytes_in_use"],
            "batches": st["batches"], "direct_batches": st["direct_batches"],
            "launch_us_per_batch": round(st["launch_ns"] / 1e3 / max(1, st["batches"]), 2), "levels": rows,

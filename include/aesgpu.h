@@ -415,6 +415,10 @@ typedef struct {
     uint32_t small_item_blocks; /* work-item size for requests of at most chunk_blocks blocks, so that
                                    several waves share a small request (0: chunk_blocks for all);
                                    at most chunk_blocks */
+    int32_t size_classes;      /* nonzero: a batch holds only requests of at most chunk_blocks blocks or
+                                  only larger ones (the head of the queue picks; the other class keeps
+                                  its order for the next slot), so small requests do not wait for
+                                  large ones in their batch; 0: one FIFO for all */
 } aes_serve_config;
 
 typedef struct {

@@ -460,7 +460,8 @@ class _ServeConfig(ctypes.Structure):
                 ("max_batch_items", ctypes.c_uint32), ("nslots", ctypes.c_int32), ("bpt", ctypes.c_int32),
                 ("wg", ctypes.c_int32), ("grid", ctypes.c_int32), ("auto_release", ctypes.c_int32),
                 ("dry_run", ctypes.c_int32), ("dry_run_seconds", ctypes.c_double), ("placement", ctypes.c_int32),
-                ("completion", ctypes.c_int32), ("small_item_blocks", ctypes.c_uint32)]
+                ("completion", ctypes.c_int32), ("small_item_blocks", ctypes.c_uint32),
+                ("size_classes", ctypes.c_int32)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -501,12 +502,14 @@ class Server:
     Device buffers are torch tensors owned by the caller (kept alive here);
     the work-list workspace and pinned staging are allocated here with torch.
     ``dry_run`` runs the admission policy with no device work (CPU only).
+    ``size_classes`` (on by default) keeps requests of at most ``chunk_blocks``
+    blocks and larger ones in separate batches.
     """
 
     def __init__(self, key_table_dev=None, in_pool=None, out_arena=None, *, n_slots=None, in_blocks=None,
                  out_blocks=None, budget_bytes=32 << 30, chunk_blocks=2048, max_batch_items=1 << 18, nslots=4,
                  bpt=4, wg=1024, grid=0, auto_release=True, dry_run=False, dry_run_seconds=0.0,
-                 placement=AES_PLACEMENT_TTABLE4, completion=0, small_item_blocks=None):
+                 placement=AES_PLACEMENT_TTABLE4, completion=0, small_item_blocks=None, size_classes=True):
         lib = _lib()
         _serve_sigs(lib)
         self._lib = lib
@@ -514,7 +517,8 @@ class Server:
                                 int(wg), int(grid), int(bool(auto_release)), int(bool(dry_run)), float(dry_run_seconds),
                                 int(placement), int(completion),
                                 # default: one wave unit (64 lanes x bpt blocks) per item of a small request
-                                int(min(64 * bpt, chunk_blocks) if small_item_blocks is None else small_item_blocks))
+                                int(min(64 * bpt, chunk_blocks) if small_item_blocks is None else small_item_blocks),
+                                int(bool(size_classes)))
         ws = lib.aes_server_workspace_bytes(ctypes.byref(self.cfg))
         st = lib.aes_server_staging_bytes(ctypes.byref(self.cfg))
         self._keep = [key_table_dev, in_pool, out_arena]

@@ -353,26 +353,43 @@ void worker_loop(aes_server* s)
         for (Slot& sl : s->slots) {
             if (sl.busy || s->pending.empty())
                 continue;
+            // Requests join in arrival order until one does not fit.  With
+            // size classes the queue's head sets the batch's class (at most
+            // chunk_blocks blocks, or more) and requests of the other class
+            // keep their place for the next slot, so a small request never
+            // waits for a large one that shares its batch.
             std::vector<Req*> batch;
+            std::deque<Req*> rest;
             uint64_t items = 0;
-            while (!s->pending.empty()) {
-                Req* q = s->pending.front();
+            bool full = false, have_class = false, small_class = false;
+            for (Req* q : s->pending) {
+                if (full) {
+                    rest.push_back(q);
+                    continue;
+                }
                 if (!valid(s, q->r)) {  // can never run: report at once
-                    s->pending.pop_front();
                     q->status = AES_SERVED_REJECTED;
                     q->done = s->now();
                     std::lock_guard<std::mutex> g(s->mu);
                     s->completed.push_back(q);
                     continue;
                 }
+                const bool small = q->r.nblocks <= s->cfg.chunk_blocks;
+                if (s->cfg.size_classes && have_class && small != small_class) {
+                    rest.push_back(q);
+                    continue;
+                }
+                have_class = true;
+                small_class = small;
                 const uint64_t need = request_items(s->cfg, q->r.nblocks);
                 const uint64_t bytes = 2 * 16 * q->r.nblocks;  // valid(): at most the budget
-                if (items + need > s->cfg.max_batch_items || bytes > s->cfg.budget_bytes - s->in_use)
-                    break;
-                uint64_t start;
-                if (!s->arena.alloc(q->r.nblocks, &start))
-                    break;
-                s->pending.pop_front();
+                uint64_t start = 0;
+                if (items + need > s->cfg.max_batch_items || bytes > s->cfg.budget_bytes - s->in_use ||
+                    !s->arena.alloc(q->r.nblocks, &start)) {
+                    full = true;
+                    rest.push_back(q);
+                    continue;
+                }
                 q->out_block = start;
                 q->admitted = s->now();
                 q->batch = (int)s->batches.load(std::memory_order_relaxed);
@@ -380,6 +397,7 @@ void worker_loop(aes_server* s)
                 items += need;
                 batch.push_back(q);
             }
+            s->pending.swap(rest);
             if (batch.empty())
                 break;
             if (s->in_use > s->max_in_use.load(std::memory_order_relaxed))

@@ -35,7 +35,7 @@ def wait_all(srv, n, timeout=30.0):
 def test_dry_run_budget_fifo_and_overlap():
     budget = 2 * 16 * 20000
     srv = aes.Server(n_slots=8, in_blocks=200000, out_blocks=60000, budget_bytes=budget, chunk_blocks=256,
-                     max_batch_items=512, nslots=3, dry_run=True, dry_run_seconds=0.002)
+                     max_batch_items=512, nslots=3, dry_run=True, dry_run_seconds=0.002, size_classes=False)
     r = requests(300, 1)
     first = srv.submit(r)
     out = wait_all(srv, 300)
@@ -50,6 +50,36 @@ def test_dry_run_budget_fifo_and_overlap():
     assert (out["done_s"] >= out["admitted_s"]).all() and (out["admitted_s"] >= out["arrival_s"]).all()
     # requests of one batch share a batch index; batches are numbered in admission order
     assert (np.diff(out["batch"]) >= 0).all()
+
+
+def test_dry_run_size_classes_keep_small_requests_out_of_large_batches():
+    """With size classes every batch holds only requests of at most
+    chunk_blocks blocks or only larger ones, each class is admitted in
+    submission order, and everything completes; without them the same queue
+    mixes the classes."""
+    chunk = 256
+    g = inputs.rng(60, 77)
+    r = np.zeros(200, dtype=aes.REQUEST_DTYPE)
+    large = g.random(200) < 0.3
+    r["nblocks"] = np.where(large, g.integers(chunk + 1, 4 * chunk, 200), g.integers(1, chunk + 1, 200))
+    r["in_block"] = 0
+    r["key_slot"] = g.integers(0, 4, 200)
+    r["decrypt"] = g.integers(0, 2, 200)
+    mixed = {}
+    for classes in (True, False):
+        srv = aes.Server(n_slots=4, in_blocks=100000, out_blocks=200000, budget_bytes=1 << 30, chunk_blocks=chunk,
+                         max_batch_items=64, nslots=2, dry_run=True, dry_run_seconds=0.001, size_classes=classes)
+        srv.submit(r)
+        out = wait_all(srv, 200)
+        srv.close()
+        assert (out["status"] == aes.AES_SERVED_DONE).all()
+        big = out["nblocks"] > chunk
+        mixed[classes] = sum(len(set(big[out["batch"] == b])) > 1 for b in np.unique(out["batch"]))
+        for cls in (True, False):
+            sel = out[big == cls]
+            assert (np.diff(sel["admitted_s"]) >= 0).all(), "each class is admitted in submission order"
+    assert mixed[True] == 0, "a batch mixed small and large requests"
+    assert mixed[False] > 0, "the single FIFO was expected to mix the classes here"
 
 
 def test_dry_run_rejects_what_can_never_run():
