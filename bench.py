@@ -501,8 +501,8 @@ def host_sweep(torch, aes, inputs, reps=20):
     pageable host buffers, plus one 1 GiB pinned buffer for the rate over the
     host link.  Wall time of the synchronous call, median of reps."""
     ks = aes.aes_expand_key(inputs.random_key(5, 128))
-    pipe = aes.HostPipe(chunk_bytes=4 * MiB, nslots=4, staging=True)
-    out = {"keybits": 128, "chunk_bytes": 4 * MiB, "nslots": 4, "sizes": []}
+    pipe = aes.HostPipe(chunk_bytes=32 * MiB, nslots=2, staging=True)
+    out = {"keybits": 128, "chunk_bytes": 32 * MiB, "nslots": 2, "sizes": []}
     big = max(PAPER_GPU_SECONDS)
     src_pin = torch.from_numpy(inputs.random_bytes(6, (big + 15) // 16 * 16)).pin_memory()
     dst_pin = torch.empty_like(src_pin).pin_memory()

@@ -185,9 +185,13 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  * Host-inclusive path (aes_pipe_*): host buffer in, host buffer out.  The
  * paper's GPU timings are of files in host memory (section 5, Tables 4-5),
  * i.e. they include the copies over the host link; this path measures and
- * serves that regime.  A buffer is cut into chunks; chunk i runs on slot
- * i mod nslots (one stream): copy to the device, the kernel in place,
- * copy back, so copies and kernels of different chunks overlap.
+ * serves that regime.  A buffer is cut into pieces of at most chunk_bytes
+ * (smaller, down to 1 MiB, when that gives every slot two pieces); piece i
+ * runs on slot i mod nslots (one stream): copy to the device, the kernel in
+ * place, copy back, so copies and kernels of different pieces overlap.  Two
+ * slots keep one copy in each direction in flight, which is what the host
+ * link rewards (on MI355X 2 x 32 MiB reached 0.90 of the link's two-way
+ * rate, 4 or 8 slots less).
  *
  * aes_pipe_config (all memory provided and owned by the caller):
  *   dev, dev_bytes:         device workspace, 16-byte aligned, at least
@@ -204,8 +208,8 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  * aes_pipe_run(p, op, rk, nr, iv, host_in, host_out, nbytes, flags):
  *   op:      AES_PIPE_ECB_ENCRYPT / AES_PIPE_ECB_DECRYPT (rk = rk_enc /
  *            rk_dec, nbytes a multiple of 16) or AES_PIPE_CTR (rk = rk_enc,
- *            iv = first counter block, any nbytes; chunk k continues the
- *            counter at iv + k*chunk_bytes/16).
+ *            iv = first counter block, any nbytes; each piece continues the
+ *            counter at iv + (its offset)/16).
  *   host_in, host_out: host pointers; host_in == host_out is allowed, any
  *            other overlap is AES_EINVAL.
  *   flags:   AES_PIPE_HOST_PINNED if both host buffers are page-locked (then

@@ -637,7 +637,7 @@ class HostPipe:
     out, chunks pipelined over ``nslots`` streams.  The device workspace and
     the pinned staging are allocated here with torch and kept alive."""
 
-    def __init__(self, chunk_bytes: int = 4 << 20, nslots: int = 4, staging: bool = True):
+    def __init__(self, chunk_bytes: int = 32 << 20, nslots: int = 2, staging: bool = True):
         import torch
         lib = _lib()
         _pipe_sigs(lib)

@@ -3,11 +3,12 @@
 //
 // The paper times files in host memory (section 5, Tables 4-5), so its GPU
 // figures include the copies over the host link.  This path runs the same
-// kernels on host buffers: the buffer is cut into chunks, and chunk i goes
-// through slot i mod N (one stream, one device chunk, one pinned staging
-// chunk per slot): host -> device copy, the kernel in place on the device
-// chunk, device -> host copy, an event.  Chunks on different slots overlap,
-// so copies in both directions and kernels run at once.  Pageable buffers go
+// kernels on host buffers: the buffer is cut into pieces of at most a chunk
+// (smaller when that gives every slot two pieces), and piece i goes through
+// slot i mod N (one stream, one device chunk, one pinned staging chunk per
+// slot): host -> device copy, the kernel in place on the device chunk,
+// device -> host copy, an event.  Pieces on different slots overlap, so
+// copies in both directions and kernels run at once.  Pageable buffers go
 // through the slot's pinned chunk (a CPU copy on each side); buffers the
 // caller allocated pinned (AES_PIPE_HOST_PINNED) are copied directly.  The
 // caller provides the device workspace and the pinned staging; the pipe
@@ -22,6 +23,8 @@
 // (hipPointerGetAttributes, hipMemGetAddressRange); anything else takes the
 // copy path.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include <cstdint>
 #include <cstring>
@@ -105,6 +108,7 @@ bool overlap_partial(const void* a, const void* b, uint64_t n)
 }
 
 constexpr uint64_t kDirectMax = 4ull << 20;
+constexpr uint64_t kMinPiece = 1ull << 20;  // smallest piece a pipelined buffer is cut into
 
 // The kernel for the bytes [off, off + len) of the message, in -> out on stream.
 hipError_t launch_piece(int op, int nr, const RoundKeys& keys, const Counter128& c0, uint64_t off, const void* in,
@@ -290,14 +294,19 @@ static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8
     }
     const size_t ns = p->slots.size();
     int rc = AES_OK;
-    const uint64_t nchunks = nbytes / p->chunk + (nbytes % p->chunk != 0);
-    for (uint64_t chunk_index = 0; chunk_index < nchunks && rc == AES_OK; ++chunk_index) {
-        const uint64_t off = chunk_index * p->chunk;  // < nbytes: no overflow
-        Slot& s = p->slots[chunk_index % ns];
+    // Pieces of at most one chunk, and small enough that every slot gets two
+    // (1 MiB at least, whole blocks): a buffer of a few chunks still overlaps
+    // its copies in and out.
+    const uint64_t spread = ((nbytes + 2 * ns - 1) / (2 * ns) + 15u) & ~(uint64_t)15u;
+    const uint64_t piece = std::min<uint64_t>(p->chunk, std::max<uint64_t>(spread, kMinPiece));
+    const uint64_t npieces = nbytes / piece + (nbytes % piece != 0);
+    for (uint64_t index = 0; index < npieces && rc == AES_OK; ++index) {
+        const uint64_t off = index * piece;  // < nbytes: no overflow
+        Slot& s = p->slots[index % ns];
         rc = finish(s, dst, staged);
         if (rc != AES_OK)
             break;
-        const uint64_t len = nbytes - off < p->chunk ? nbytes - off : p->chunk;
+        const uint64_t len = nbytes - off < piece ? nbytes - off : piece;
         const void* h2d_src = src + off;
         if (staged) {
             std::memcpy(s.pin, src + off, len);

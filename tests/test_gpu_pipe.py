@@ -97,6 +97,35 @@ def test_pipe_pinned_small_buffers_run_on_host_memory(oracle_lib):
         p.close()
 
 
+def test_pipe_pieces_smaller_than_the_chunk(oracle_lib):
+    """With the default 2 x 32 MiB pipe a buffer of a few MiB is cut into
+    1-2 MiB pieces (two per slot) so its copies still overlap: ECB and CTR
+    over pinned and pageable buffers with a ragged last piece equal the
+    oracle, the CTR counter continuing at every piece offset."""
+    torch = cuda()
+    key = inputs.random_key(831, 128)
+    ks = aes.aes_expand_key(key)
+    iv = bytes([0xff] * 8 + [0xfe] + [0xff] * 7)
+    p = aes.HostPipe()
+    try:
+        for n in ((8 << 20) + 48, (5 << 20) + 16 * 7, (20 << 20) + 16):
+            x = inputs.random_bytes(832 + n % 97, n)
+            want = oracle_lib.ecb_encrypt(key, x)
+            got = p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x)                      # pageable, staged
+            assert_same(got, want, "staged enc n=%d" % n)
+            src = torch.from_numpy(x).pin_memory()
+            dst = torch.zeros(n, dtype=torch.uint8).pin_memory()
+            p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, src, out=dst)                 # pinned, copied directly
+            assert_same(dst.numpy(), want, "pinned enc n=%d" % n)
+            p.run(aes.AES_PIPE_ECB_DECRYPT, ks, dst, out=dst)
+            assert_same(dst.numpy(), x, "pinned dec in place n=%d" % n)
+            m = n - 3
+            got = p.run(aes.AES_PIPE_CTR, ks, x[:m], iv=iv)
+            assert_same(got, oracle_lib.ctr_crypt(key, iv, x[:m]), "ctr n=%d" % m)
+    finally:
+        p.close()
+
+
 def test_pipe_ctr_across_chunks(oracle_lib, pipe):
     key = inputs.random_key(820, 128)
     ks = aes.aes_expand_key(key)
