@@ -252,13 +252,16 @@ def test_create_rejects_bad_configs():
 
 # ------------------------------------------------------------------ GPU part
 @pytest.mark.gpu
-@pytest.mark.parametrize("completion,placement", [(aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE4),
-                                                  (aes.AES_SERVE_COMPLETION_EVENTS, aes.AES_PLACEMENT_TTABLE4),
-                                                  (aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE2)])
-def test_native_served_results_equal_the_request_alone(oracle_lib, completion, placement):
+@pytest.mark.parametrize("completion,placement,classes", [
+    (aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE4, True),
+    (aes.AES_SERVE_COMPLETION_EVENTS, aes.AES_PLACEMENT_TTABLE4, True),
+    (aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE2, True),
+    (aes.AES_SERVE_COMPLETION_AUTO, aes.AES_PLACEMENT_TTABLE4, False)])
+def test_native_served_results_equal_the_request_alone(oracle_lib, completion, placement, classes):
     """Every served request equals the request run alone (and the oracle on
     samples), whichever way the worker sees batches finish (completion words
-    written by the streams, or events) and with the 2-table batch kernel."""
+    written by the batch kernel, or events), with the 2-table batch kernel,
+    and with size classes or one FIFO."""
     import torch
     from paper_1902_05234_amd import batch
     pool = inputs.key_pool(6, 32)
@@ -266,7 +269,8 @@ def test_native_served_results_equal_the_request_alone(oracle_lib, completion, p
     in_pool = inputs.device_random_bytes(6, 64 << 20)
     out_arena = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda")
     srv = aes.Server(kt, in_pool, out_arena, budget_bytes=512 << 20, chunk_blocks=256, max_batch_items=1 << 14,
-                     nslots=4, auto_release=False, completion=completion, placement=placement)
+                     nslots=4, auto_release=False, completion=completion, placement=placement,
+                     size_classes=classes)
     r = requests(500, 4, max_blocks=20000, pool_blocks=in_pool.numel() // 16, slots=len(pool))
     srv.submit(r[:250])
     time.sleep(0.001)
