@@ -361,13 +361,11 @@ void worker_loop(aes_server* s)
             std::vector<Req*> batch;
             std::deque<Req*> rest;
             uint64_t items = 0;
-            bool full = false, have_class = false, small_class = false;
-            for (Req* q : s->pending) {
-                if (full) {
-                    rest.push_back(q);
-                    continue;
-                }
+            bool have_class = false, small_class = false, untouched = true;
+            for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+                Req* q = *it;
                 if (!valid(s, q->r)) {  // can never run: report at once
+                    untouched = false;
                     q->status = AES_SERVED_REJECTED;
                     q->done = s->now();
                     std::lock_guard<std::mutex> g(s->mu);
@@ -376,6 +374,7 @@ void worker_loop(aes_server* s)
                 }
                 const bool small = q->r.nblocks <= s->cfg.chunk_blocks;
                 if (s->cfg.size_classes && have_class && small != small_class) {
+                    untouched = false;
                     rest.push_back(q);
                     continue;
                 }
@@ -386,10 +385,11 @@ void worker_loop(aes_server* s)
                 uint64_t start = 0;
                 if (items + need > s->cfg.max_batch_items || bytes > s->cfg.budget_bytes - s->in_use ||
                     !s->arena.alloc(q->r.nblocks, &start)) {
-                    full = true;
-                    rest.push_back(q);
-                    continue;
+                    if (!untouched)  // the batch is full: the rest keeps its order
+                        rest.insert(rest.end(), it, s->pending.end());
+                    break;
                 }
+                untouched = false;
                 q->out_block = start;
                 q->admitted = s->now();
                 q->batch = (int)s->batches.load(std::memory_order_relaxed);
@@ -397,7 +397,8 @@ void worker_loop(aes_server* s)
                 items += need;
                 batch.push_back(q);
             }
-            s->pending.swap(rest);
+            if (!untouched)
+                s->pending.swap(rest);
             if (batch.empty())
                 break;
             if (s->in_use > s->max_in_use.load(std::memory_order_relaxed))
