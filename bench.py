@@ -19,7 +19,8 @@ before timing starts.  Prints ONE JSON line:
                vs per-message plain launches and vs the bulk-equivalent rate
   sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB (device
                time: graph replays up to 64 MiB, event-timed launches above), plus
-               an all-zero control, CTR and CBC decryption at 1 GiB
+               an all-zero control, CTR and CBC decryption at 1 GiB, and CBC
+               encryption of 1 GiB as 2^18 independent 4 KiB messages
   host_path    the paper's file sizes (1,202 ... 1,190,402 bytes) host buffer
                in, host buffer out (host-link transfers included), pinned and
                pageable, beside the paper's own GPU times; and the 1 GiB
@@ -438,6 +439,14 @@ def launch_ms(torch, fn, n):
     return sorted(tm.ms())[reps // 2]
 
 
+def cbc_records(ms):
+    """aes_cbc_msg records (aes.CBC_MSG_DTYPE) of a CBC message set."""
+    from paper_1902_05234_amd import aes
+    recs = np.zeros(len(ms), dtype=aes.CBC_MSG_DTYPE)
+    recs["in_block"], recs["out_block"], recs["nblocks"], recs["iv"] = ms.in_block, ms.out_block, ms.nblocks, ms.iv
+    return recs
+
+
 def sweep(torch, aes, inputs, sizes):
     out = {}
     buf_in = inputs.device_random_bytes(3, max(sizes))
@@ -469,6 +478,14 @@ def sweep(torch, aes, inputs, sizes):
     # preceding ciphertext block
     ms = timed10(lambda: aes.aes_cbc_decrypt(ks.rk_dec, ks.nr, bytes(16), xi, xo))
     out["aes128_cbc_dec_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    # CBC encryption across independent messages: the buffer as 4 KiB
+    # messages (one chain per lane, 2^18 of them at 1 GiB), each with its own
+    # initialisation vector
+    nm = n // 4096
+    msgs = torch.from_numpy(cbc_records(inputs.cbc_equal_messages(3, nm, 256)).view(np.uint8)).to("cuda")
+    ms = timed10(lambda: aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, nm, xi, xo))
+    out["aes128_cbc_enc_4KiB_msgs_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    del msgs
     # structured control, last because it overwrites the input: in an
     # all-zero buffer every block is the same, so every lane reads the same
     # table entry in every round (LDS broadcast); random data spreads the
@@ -848,13 +865,15 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host-inclusive file-size sweep")
     ap.add_argument("--serve-levels", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9,1.0")
     ap.add_argument("--serve-requests", type=int, default=20000)
-    ap.add_argument("--profile", nargs="?", const="bulk", choices=("bulk", "mid", "corun", "corun-sweep", "ctr", "variants", "host"),
+    ap.add_argument("--profile", nargs="?", const="bulk",
+                    choices=("bulk", "mid", "corun", "corun-sweep", "ctr", "cbc-msgs", "variants", "host"),
                     default=None,
                     help="bulk: only a few copy and 1 GiB launches; mid: graph-replayed AES-128 encryptions of "
                          "64 KiB ... 32 MiB and of a 16-byte copy (for rocprofv3 kernel traces); corun: the "
                          "bitsliced kernel beside the 4-table kernel on two streams, 30 steps (for a kernel "
                          "trace); corun-sweep: their sustained rates over bitsliced shares 0 ... 0.24; ctr: 1 GiB CTR and ECB "
-                         "encryptions in turn (for counters); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
+                         "encryptions in turn (for counters); cbc-msgs: 3 copies of 1 GiB, then CBC encryption of 1 GiB as "
+                         "2^18 messages of 4 KiB and ECB encryption of the same buffer, in turn (for counters); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
                          "and the bitsliced kernel at 1 GiB (for counters); host: the host-inclusive file-size sweep "
                          "only (for a kernel and copy trace)")
     args = ap.parse_args()
@@ -912,6 +931,22 @@ def main():
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
         torch.cuda.synchronize()
         log("ctr profile launches done")
+        return
+    if args.profile == "cbc-msgs":
+        # CBC encryption across 2^18 independent 4 KiB messages (one chain per
+        # lane, default shape) beside ECB encryption of the same 1 GiB
+        x = inputs.device_random_bytes(1, GiB)
+        y = torch.empty_like(x)
+        ks = aes.aes_expand_key(inputs.random_key(1, 128))
+        nm = GiB // 4096
+        msgs = torch.from_numpy(cbc_records(inputs.cbc_equal_messages(3, nm, 256)).view(np.uint8)).to("cuda")
+        for _ in range(3):
+            aes.aes_device_copy(x, y)  # known bytes: the counters' calibration
+        for _ in range(max(1, args.steps)):
+            aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, nm, x, y)
+            aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
+        torch.cuda.synchronize()
+        log("cbc-msgs profile launches done")
         return
     if args.profile:
         x = inputs.device_random_bytes(1, GiB)

@@ -147,7 +147,8 @@ int aes_ctr_crypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, uint64_
  * aes_cbc_decrypt -- CBC decryption (section 3.1.2, eq 2, read as
  * C_i = cipher(P_i XOR C_{i-1}) with C_0 = iv): P_i = invcipher(C_i) XOR
  * C_{i-1}.  Every block is independent, so this is the parallel direction
- * of CBC; encryption is sequential within a message and is not offered.
+ * of CBC; encryption is sequential within a message (aes_cbc_encrypt_msgs
+ * runs many messages side by side).
  *   rk:      host pointer to the DECRYPTION schedule (rk_dec), copied.
  *   nr:      10, 12 or 14.
  *   iv:      host pointer to the 16-byte initialisation vector (C_0).  To
@@ -162,6 +163,57 @@ int aes_cbc_decrypt(const uint32_t *rk, int nr, const uint8_t *iv, const void *i
                     void *stream);
 int aes_cbc_decrypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, const void *in, void *out, size_t nblocks,
                             const aes_variant *variant, void *stream);
+
+/*
+ * aes_cbc_encrypt_msgs -- CBC encryption (section 3.1.2, eq 2, read as
+ * C_i = cipher(P_i XOR C_{i-1}) with C_0 = iv) of many independent messages
+ * under one key, in one launch.  Within a message each block needs the
+ * previous ciphertext block, so a message cannot be split (Table 1 marks
+ * CBC encryption unsuitable for parallel work); the parallelism is across
+ * messages: each message is one chain, walked by one GPU lane.
+ *   rk:        host pointer to the ENCRYPTION schedule (rk_enc), copied.
+ *   nr:        10, 12 or 14.
+ *   msgs_dev:  device array of nmsgs aes_cbc_msg, 16-byte aligned.  Message
+ *              m encrypts blocks [in_block, in_block + nblocks) of the input
+ *              arena into blocks [out_block, out_block + nblocks) of the
+ *              output arena, starting its chain from iv (C_0; to continue a
+ *              message, pass its last ciphertext block so far).
+ *   in_base, in_blocks / out_base, out_blocks: device arenas, 16-byte
+ *              aligned, sizes in blocks.  The same arena for both is
+ *              allowed; any other overlap of the two is AES_EINVAL.  A
+ *              message may run in place (equal ranges in one arena); the
+ *              output range of a message must not overlap another message's
+ *              input or output range (not checked: such messages get
+ *              undefined results, and no access leaves the arenas).
+ *   rejected_dev: NULL or a device uint32 (4-byte aligned) to which the
+ *              kernel adds the number of messages it skipped: a range
+ *              outside its arena or a nonzero reserved field.  A skipped
+ *              message's output is left untouched.
+ *   nmsgs:     0 is a no-op returning AES_OK.
+ * One chain has one block in flight, so a launch keeps every compute unit
+ * busy only with about 2^18 messages or more; fewer are bound by the latency
+ * of a block's rounds.  The 64 consecutive entries that one wave walks take
+ * as long as the longest of them: list messages of similar length together.
+ * Asynchronous on stream.
+ */
+typedef struct {
+    uint64_t in_block;
+    uint64_t out_block;
+    uint64_t nblocks;
+    uint64_t reserved; /* 0 */
+    uint8_t iv[16];
+} aes_cbc_msg;
+int aes_cbc_encrypt_msgs(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs, const void *in_base,
+                         size_t in_blocks, void *out_base, size_t out_blocks, uint32_t *rejected_dev, void *stream);
+/* Same with an explicit variant: bpt = blocks a lane loads and stores at once
+ * (1, 2, 4 or 8), wg, a table placement (not bitsliced), grid (0 = as many
+ * workgroups as fit on every compute unit, no more than the messages need).
+ * AES_EINVAL outside that.  aes_cbc_encrypt_msgs takes bpt 8, the 4-table
+ * placement and the smallest workgroup (up to 1024 threads) that gives every
+ * compute unit the same number of 64-message waves. */
+int aes_cbc_encrypt_msgs_variant(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs,
+                                 const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
+                                 uint32_t *rejected_dev, const aes_variant *variant, void *stream);
 
 /*
  * aes_roof_probe -- the measured roofs beside the published ones.

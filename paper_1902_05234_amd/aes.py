@@ -30,7 +30,9 @@ MSG_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u
                       ("key_slot", "<u4"), ("decrypt", "<u4")])
 AES_MAX_ITEM_BLOCKS = 1 << 24  # largest work item (blocks), as in the C header
 ITEM_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u4"), ("key_slot", "<u4")])
-assert MSG_DTYPE.itemsize == 32 and ITEM_DTYPE.itemsize == 24
+CBC_MSG_DTYPE = np.dtype([("in_block", "<u8"), ("out_block", "<u8"), ("nblocks", "<u8"), ("reserved", "<u8"),
+                          ("iv", "u1", (16,))])
+assert MSG_DTYPE.itemsize == 32 and ITEM_DTYPE.itemsize == 24 and CBC_MSG_DTYPE.itemsize == 48
 
 
 class AesError(RuntimeError):
@@ -99,6 +101,9 @@ def _lib() -> ctypes.CDLL:
                 "aes_cbc_decrypt": ([_u32p, _c_i, _u8p, _c_p, _c_p, _c_sz, _c_p], _c_i),
                 "aes_cbc_decrypt_variant": ([_u32p, _c_i, _u8p, _c_p, _c_p, _c_sz, ctypes.POINTER(_Variant), _c_p],
                                             _c_i),
+                "aes_cbc_encrypt_msgs": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_p], _c_i),
+                "aes_cbc_encrypt_msgs_variant": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
+                                                  ctypes.POINTER(_Variant), _c_p], _c_i),
                 "aes_tune_set": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_tune_get": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_size_bucket": ([_c_sz], _c_i),
@@ -132,7 +137,7 @@ def exported_symbols():
     """Names this binding expects the library to export."""
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
             "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
-            "aes_cbc_decrypt_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
+            "aes_cbc_decrypt_variant", "aes_cbc_encrypt_msgs", "aes_cbc_encrypt_msgs_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
             "aes_ecb_batch", "aes_ecb_batch_noalloc", "aes_batch_max_grid", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
@@ -304,6 +309,32 @@ def aes_cbc_decrypt_variant(rk, nr: int, iv: bytes, inp, out, variant: Variant, 
                             stream=None):
     v = variant._c()
     return _cbc(_lib().aes_cbc_decrypt_variant, rk, nr, iv, inp, out, nblocks, stream, ctypes.byref(v))
+
+
+def aes_cbc_encrypt_msgs(rk, nr: int, msgs_dev, nmsgs: int, in_base, out_base, rejected_dev=None,
+                         variant: Variant | None = None, stream=None):
+    """CBC encryption of nmsgs independent messages described by the device
+    tensor ``msgs_dev`` (CBC_MSG_DTYPE records) between the arenas ``in_base``
+    and ``out_base``; rk is the encryption schedule.  ``rejected_dev`` (a
+    device int32/uint32 tensor, or None) receives the count of skipped
+    messages."""
+    nmsgs = int(nmsgs)
+    if nmsgs < 0 or _bytes_of(msgs_dev, "msgs_dev") < nmsgs * CBC_MSG_DTYPE.itemsize:
+        raise ValueError("message tensor smaller than nmsgs records")
+    rej = 0
+    if rejected_dev is not None:
+        if _bytes_of(rejected_dev, "rejected_dev") < 4:
+            raise ValueError("the rejected counter needs 4 bytes")
+        rej = rejected_dev.data_ptr()
+    rk = _u32_array(rk, 4 * (int(nr) + 1))
+    args = [rk.ctypes.data_as(_u32p), int(nr), msgs_dev.data_ptr(), nmsgs, in_base.data_ptr(),
+            _blocks_of(in_base, "in_base"), out_base.data_ptr(), _blocks_of(out_base, "out_base"), rej]
+    if variant is None:
+        _check(_lib().aes_cbc_encrypt_msgs(*args, _stream_handle(stream)))
+    else:
+        v = variant._c()
+        _check(_lib().aes_cbc_encrypt_msgs_variant(*args, ctypes.byref(v), _stream_handle(stream)))
+    return out_base
 
 
 def aes_tune_set(nr: int, decrypt: bool, nblocks: int, variant: Variant):

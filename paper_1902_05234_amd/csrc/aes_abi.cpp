@@ -15,6 +15,7 @@
 #include <mutex>
 
 #include "../../include/aesgpu.h"
+#include "aes_cbc_msgs.hpp"
 #include "aes_internal.hpp"
 #include "aes_tables.hpp"
 
@@ -273,6 +274,71 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     return AES_OK;
 }
 
+// Shape of aes_cbc_encrypt_msgs when the caller names none: 8 blocks (one
+// 128-byte line) per lane per load and store and the 4-table placement (one
+// workgroup per CU), with workgroups just large enough to give every CU the
+// same number of 64-message waves, up to 1024 threads: a smaller message
+// list then still spreads over all CUs instead of filling a few.
+aes_variant cbc_msgs_default(size_t nmsgs, int cus)
+{
+    const uint64_t units = (nmsgs + 63u) / 64u;
+    const uint64_t per_cu = cus > 0 ? (units + (uint64_t)cus - 1) / (uint64_t)cus : 16u;
+    const int wg = (int)std::min<uint64_t>(1024u, 64u * std::max<uint64_t>(per_cu, 1u));
+    return aes_variant{8, wg, AES_PLACEMENT_TTABLE4, 0};
+}
+
+// v == nullptr: the default shape for this many messages (cbc_msgs_default).
+int run_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs, const void* in_base,
+                         size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev,
+                         const aes_variant* v, void* stream)
+{
+    if (!valid_nr(nr))
+        return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
+    if (rk == nullptr)
+        return fail(AES_EINVAL, "null round-key pointer");
+    if (nmsgs == 0)
+        return AES_OK;
+    if (msgs_dev == nullptr || in_base == nullptr || out_base == nullptr)
+        return fail(AES_EINVAL, "null message list or arena with nmsgs=%zu", nmsgs);
+    if (nmsgs > (SIZE_MAX / sizeof(aes_cbc_msg)))
+        return fail(AES_EINVAL, "nmsgs=%zu too large", nmsgs);
+    if ((reinterpret_cast<uintptr_t>(msgs_dev) | reinterpret_cast<uintptr_t>(in_base) |
+         reinterpret_cast<uintptr_t>(out_base)) & 15u)
+        return fail(AES_EALIGN, "message list and arenas must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(rejected_dev) & 3u)
+        return fail(AES_EALIGN, "the rejected counter must be 4-byte aligned");
+    if (in_blocks > (SIZE_MAX >> 5) || out_blocks > (SIZE_MAX >> 5))
+        return fail(AES_EINVAL, "arena sizes too large (%zu / %zu blocks)", in_blocks, out_blocks);
+    // each arena with its own length: only the very same arena may be shared
+    const uintptr_t ib = reinterpret_cast<uintptr_t>(in_base), ob = reinterpret_cast<uintptr_t>(out_base);
+    if (ib != ob && ib < ob + (uint64_t)out_blocks * 16u && ob < ib + (uint64_t)in_blocks * 16u)
+        return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
+    if (v != nullptr) {
+        if (v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != 8)
+            return fail(AES_EINVAL, "bpt (blocks a lane loads at once) must be 1, 2, 4 or 8, got %d", v->bpt);
+        aes_variant shape_only = *v;
+        shape_only.bpt = 1;
+        int rc = check_variant(&shape_only);
+        if (rc != AES_OK)
+            return rc;
+        if (v->placement == AES_PLACEMENT_BITSLICED)
+            return fail(AES_EINVAL, "CBC encryption runs on the table placements only (not bitsliced)");
+    }
+    RoundKeys keys{};
+    std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
+    int cus = device_cu_count();
+    if (cus <= 0)
+        return fail(AES_EHIP, "cannot query the current HIP device");
+    const aes_variant chosen = v != nullptr ? *v : cbc_msgs_default(nmsgs, cus);
+    v = &chosen;
+    LaunchShape shape{v->bpt, v->wg, v->grid};
+    hipError_t e = launch_cbc_encrypt_msgs(shape, v->placement, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base,
+                                           out_blocks, rejected_dev, keys, cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "CBC encryption kernel launch");
+    return AES_OK;
+}
+
 // Workgroups of a batch launch at most: cfg.grid, or as many as fit on every
 // CU at once for the configured variant.
 int batch_max_grid(const aes_batch_config& c, int* out)
@@ -367,6 +433,7 @@ int device_cu_count()
 using namespace aesgpu;
 
 static_assert(sizeof(aes_work_item) == sizeof(WorkItem), "work item layout");
+static_assert(sizeof(aes_cbc_msg) == 48 && offsetof(aes_cbc_msg, iv) == 32, "CBC message layout");
 static_assert(offsetof(aes_work_item, nblocks) == offsetof(WorkItem, nblocks), "work item layout");
 static_assert(offsetof(aes_work_item, key_slot) == offsetof(WorkItem, key_slot), "work item layout");
 
@@ -489,6 +556,23 @@ int aes_cbc_decrypt_variant(const uint32_t* rk, int nr, const uint8_t* iv, const
     if (variant == nullptr)
         return fail(AES_EINVAL, "null variant");
     return run_cbc_decrypt(rk, nr, iv, in, out, nblocks, variant, stream);
+}
+
+int aes_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs, const void* in_base,
+                         size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev, void* stream)
+{
+    return run_cbc_encrypt_msgs(rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                                nullptr, stream);
+}
+
+int aes_cbc_encrypt_msgs_variant(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs,
+                                 const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks,
+                                 uint32_t* rejected_dev, const aes_variant* variant, void* stream)
+{
+    if (variant == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    return run_cbc_encrypt_msgs(rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                                variant, stream);
 }
 
 int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant* v)

@@ -1,0 +1,183 @@
+// aes_cbc_msgs.hip -- CBC encryption of many independent messages.
+//
+// CBC encryption (section 3.1.2, eq 2, read with the block cipher: C_i =
+// cipher(P_i XOR C_{i-1}), C_0 the initialisation vector) is a chain: block i
+// needs the ciphertext of block i - 1, which is why the paper's Table 1 marks
+// the mode unsuitable for parallel work within one message.  Separate
+// messages are separate chains, so this kernel gives each message one lane:
+// a wave walks 64 messages side by side, block by block, with the replicated
+// T-tables in LDS as in ECB and the one key in scalar registers.
+//
+// A lane loads G consecutive blocks of its message at once (16G contiguous
+// bytes; G = 8 is one 128-byte line), one group ahead of the rounds, and
+// stores a group's G ciphertext blocks together.  The 64 lanes of a wave
+// touch 64 different lines per access, so the stores are plain, not
+// non-temporal as in ECB: the L2 then merges a lane's 16-byte blocks into
+// whole lines before they leave it, where non-temporal 16-byte stores to
+// scattered lines went out one by one (about 4x slower: 330 against 1400 GB/s
+// for 2^18 messages of 4 KiB).  A chain has one block in the rounds at a
+// time, so the LDS is kept busy only when enough waves walk chains at once
+// (16 per CU with the 4-table placement: 2^18 messages on 256 CUs); with
+// fewer messages a launch is bound by the latency of one block's rounds.  A
+// wave lasts as long as the longest of its 64 messages.
+#include "aes_cbc_msgs.hpp"
+#include "aes_ecb_kernel.hpp"
+
+namespace aesgpu {
+
+namespace {
+
+// Layout of aes_cbc_msg (aesgpu.h), read as three 16-byte loads.
+struct CbcMsg {
+    uint64_t in_block;
+    uint64_t out_block;
+    uint64_t nblocks;
+    uint64_t reserved;
+    uint4 iv;
+};
+static_assert(sizeof(CbcMsg) == 48, "aes_cbc_msg layout");
+
+__device__ __forceinline__ uint4 xor4m(uint4 a, uint4 b) { return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w); }
+
+template <int G>
+__device__ __forceinline__ void load_group(uint4 (&v)[G], const uint4* src, uint64_t first, uint64_t nb)
+{
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (first + k < nb)
+            v[k] = src[first + k];
+}
+
+template <int NR, int G, int PL>
+__global__ __launch_bounds__(1024) void cbc_enc_msgs_kernel(const CbcMsg* __restrict__ msgs, uint64_t nmsgs,
+                                                            const uint4* in, uint64_t in_blocks, uint4* out,
+                                                            uint64_t out_blocks, uint32_t* rejected, RoundKeys rk)
+{
+    __shared__ __align__(16) uint32_t lds[Layout<PL, false>::words];
+    fill_tables<PL, false>(lds, &c_tables);
+    __syncthreads();
+    const LaneBases<PL, false> lb(threadIdx.x);
+    auto key = [&](int i) { return rk.w[i]; };
+
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t waves_per_grid = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t units = (nmsgs + 63u) / 64u;
+    for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv < units;
+         wv += waves_per_grid) {
+        const uint64_t m = wv * 64u + lane;
+        uint64_t nb = 0;
+        const uint4* src = in;
+        uint4* dst = out;
+        uint4 chain = make_uint4(0u, 0u, 0u, 0u);
+        if (m < nmsgs) {
+            const CbcMsg d = msgs[m];
+            // both ranges inside their arenas, written so that no sum can wrap
+            const bool ok = d.reserved == 0 && d.in_block <= in_blocks && d.nblocks <= in_blocks - d.in_block &&
+                            d.out_block <= out_blocks && d.nblocks <= out_blocks - d.out_block;
+            if (ok) {
+                nb = d.nblocks;
+                src = in + d.in_block;
+                dst = out + d.out_block;
+                chain = d.iv;
+            } else if (rejected != nullptr) {
+                atomicAdd(rejected, 1u);
+            }
+        }
+        uint4 cur[G];
+        load_group<G>(cur, src, 0, nb);
+        // each lane walks its own chain; lanes whose message has ended idle
+        // until the wave's longest message is done
+        for (uint64_t g = 0; g < nb; g += G) {
+            uint4 nxt[G];
+            load_group<G>(nxt, src, g + G, nb);
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k == 0 || g + k < nb) {
+                    chain = crypt_block<NR, false, PL>(xor4m(cur[k], chain), lds, lb, key);
+                    cur[k] = chain;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                if (k == 0 || g + k < nb)
+                    dst[g + k] = cur[k];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                cur[k] = nxt[k];
+        }
+    }
+}
+
+template <int NR, int G, int PL>
+hipError_t launch_one_cbc_msgs(const CbcMsg* msgs, uint64_t nmsgs, const void* in, uint64_t in_blocks, void* out,
+                               uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk, const LaunchShape& shape,
+                               int cus, hipStream_t stream)
+{
+    auto kern = cbc_enc_msgs_kernel<NR, G, PL>;
+    int grid = shape.grid;
+    if (grid <= 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                                    shape.wg, 0);
+        if (e != hipSuccess)
+            return e;
+        grid = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    // no more workgroups than the 64-message wave units can keep busy
+    const uint64_t waves = (nmsgs + 63u) / 64u;
+    const uint64_t per_group = (uint64_t)shape.wg / 64u;
+    const uint64_t needed = (waves + per_group - 1) / per_group;
+    if ((uint64_t)grid > needed)
+        grid = (int)needed;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(shape.wg), 0, stream, msgs, nmsgs, static_cast<const uint4*>(in),
+                       in_blocks, static_cast<uint4*>(out), out_blocks, rejected, rk);
+    return hipGetLastError();
+}
+
+template <int G, int PL>
+hipError_t launch_cbc_msgs_nr(int nr, const CbcMsg* msgs, uint64_t nmsgs, const void* in, uint64_t in_blocks,
+                              void* out, uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk,
+                              const LaunchShape& shape, int cus, hipStream_t stream)
+{
+    switch (nr) {
+    case 10: return launch_one_cbc_msgs<10, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case 12: return launch_one_cbc_msgs<12, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case 14: return launch_one_cbc_msgs<14, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PL>
+hipError_t launch_cbc_msgs_g(int nr, const CbcMsg* msgs, uint64_t nmsgs, const void* in, uint64_t in_blocks,
+                             void* out, uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk,
+                             const LaunchShape& shape, int cus, hipStream_t stream)
+{
+    switch (shape.bpt) {
+    case 1: return launch_cbc_msgs_nr<1, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case 2: return launch_cbc_msgs_nr<2, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case 4: return launch_cbc_msgs_nr<4, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case 8: return launch_cbc_msgs_nr<8, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cbc_encrypt_msgs(const LaunchShape& shape, int placement, int nr, const void* msgs, uint64_t nmsgs,
+                                   const void* in, uint64_t in_blocks, void* out, uint64_t out_blocks,
+                                   uint32_t* rejected, const RoundKeys& rk, int cus, hipStream_t stream)
+{
+    const CbcMsg* m = static_cast<const CbcMsg*>(msgs);
+    switch (placement) {
+    case kPlace4:
+        return launch_cbc_msgs_g<kPlace4>(nr, m, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    case kPlace2:
+        return launch_cbc_msgs_g<kPlace2>(nr, m, nmsgs, in, in_blocks, out, out_blocks, rejected,
+                                          inner_keys_rotr8(rk, nr), shape, cus, stream);
+    case kPlace1:
+        return launch_cbc_msgs_g<kPlace1>(nr, m, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace aesgpu

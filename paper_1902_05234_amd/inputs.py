@@ -12,7 +12,11 @@ section 5, Tables 4-5; uniform random bytes stand in for them):
   whole 16-byte blocks, key size uniform over {128, 192, 256}, direction
   encrypt/decrypt with probability 1/2 each;
 * serving mix: Poisson arrivals; sizes 80 % log-uniform 64 B - 16 KiB and
-  20 % log-uniform 1 - 64 MiB (rounded to 16 B); keys drawn from a pool.
+  20 % log-uniform 1 - 64 MiB (rounded to 16 B); keys drawn from a pool;
+* CBC message sets: many independent messages under one key, each with a
+  uniform random 16-byte initialisation vector; either a ragged set (lengths
+  uniform in 0 .. max blocks, inputs packed in order with gaps, outputs in a
+  shuffled order with gaps) or equal lengths back to back.
 """
 from __future__ import annotations
 
@@ -122,3 +126,48 @@ def device_random_bytes(seed: int, nbytes: int, device="cuda"):
     g = torch.Generator(device=device)
     g.manual_seed(int(np.random.SeedSequence([BASE_SEED, 6, seed]).generate_state(1)[0]))
     return torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=device, generator=g)
+
+
+@dataclass
+class CbcMessageSet:
+    """Positions (in 16-byte blocks) and initialisation vectors of independent
+    messages in an input and an output arena."""
+
+    nblocks: np.ndarray    # uint64 [n]
+    in_block: np.ndarray   # uint64 [n]
+    out_block: np.ndarray  # uint64 [n]
+    iv: np.ndarray         # uint8 [n, 16]
+    in_blocks: int         # arena sizes
+    out_blocks: int
+
+    def __len__(self) -> int:
+        return int(self.nblocks.size)
+
+
+def cbc_message_set(seed: int, n: int, max_blocks: int) -> CbcMessageSet:
+    """A ragged set: the first min(n, 10) messages have 0 .. 9 blocks, the
+    rest uniform in [0, max_blocks]; inputs in order with gaps of 0 .. 3
+    blocks, outputs in a random order with gaps of 0 .. 3 blocks."""
+    g = rng(7, seed)
+    nb = g.integers(0, max_blocks + 1, size=n).astype(np.uint64)
+    k = min(n, 10)
+    nb[:k] = np.arange(k, dtype=np.uint64)
+    gap_in = g.integers(0, 4, size=n).astype(np.uint64)
+    in_block = np.cumsum(gap_in + nb) - nb
+    order = g.permutation(n)
+    gap_out = g.integers(0, 4, size=n).astype(np.uint64)
+    ends = np.cumsum(gap_out + nb[order])
+    out_block = np.empty(n, dtype=np.uint64)
+    out_block[order] = ends - nb[order]
+    iv = g.integers(0, 256, size=(n, 16), dtype=np.uint8)
+    return CbcMessageSet(nb, in_block.astype(np.uint64), out_block, iv,
+                         int(in_block[-1] + nb[-1]) + 3 if n else 0, int(ends[-1]) + 3 if n else 0)
+
+
+def cbc_equal_messages(seed: int, n: int, blocks: int) -> CbcMessageSet:
+    """n messages of ``blocks`` blocks each, back to back in both arenas at
+    the same positions (message m at block m * blocks)."""
+    g = rng(8, seed)
+    pos = (np.arange(n, dtype=np.uint64) * np.uint64(blocks))
+    iv = g.integers(0, 256, size=(n, 16), dtype=np.uint8)
+    return CbcMessageSet(np.full(n, blocks, dtype=np.uint64), pos, pos.copy(), iv, n * blocks, n * blocks)

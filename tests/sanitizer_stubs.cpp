@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "aes_batch_signal.hpp"
+#include "aes_cbc_msgs.hpp"
 #include "aes_internal.hpp"
 
 namespace aesgpu {
@@ -34,6 +35,12 @@ hipError_t launch_ctr(const LaunchShape&, int, int, const void*, void*, uint64_t
 
 hipError_t launch_cbc_decrypt(const LaunchShape&, int, int, const void*, void*, uint64_t, const uint8_t*,
                               const RoundKeys&, int, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cbc_encrypt_msgs(const LaunchShape&, int, int, const void*, uint64_t, const void*, uint64_t, void*,
+                                   uint64_t, uint32_t*, const RoundKeys&, int, hipStream_t)
 {
     return hipErrorInvalidValue;
 }

@@ -262,6 +262,43 @@ def test_cbc_argument_checks_before_any_device_call():
     assert lib.aes_cbc_decrypt_variant(rk, 10, iv, A, B, 4, None, None) == aes.AES_EINVAL
 
 
+def test_cbc_encrypt_msgs_argument_checks_before_any_device_call():
+    lib = aes._lib()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    M, A, B = 0x30000, 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+    enc = lib.aes_cbc_encrypt_msgs
+
+    def var(**kw):
+        return aes.ctypes.byref(aes.Variant(**kw)._c())
+
+    assert enc(rk, 11, M, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert enc(None, 10, M, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert enc(rk, 10, M, 0, A, 64, B, 64, None, None) == aes.AES_OK            # no messages: no launch
+    assert enc(rk, 10, None, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert enc(rk, 10, M, 4, None, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert enc(rk, 10, M, 4, A, 64, None, 64, None, None) == aes.AES_EINVAL
+    assert enc(rk, 10, M + 8, 4, A, 64, B, 64, None, None) == aes.AES_EALIGN    # message list
+    assert enc(rk, 10, M, 4, A + 4, 64, B, 64, None, None) == aes.AES_EALIGN
+    assert enc(rk, 10, M, 4, A, 64, B + 8, 64, None, None) == aes.AES_EALIGN
+    assert enc(rk, 10, M, 4, A, 64, B, 64, 0x40002, None) == aes.AES_EALIGN    # rejected counter
+    # arenas: each with its own length; only the very same arena may be shared
+    assert enc(rk, 10, M, 4, A, 4096, A + 1024, 16, None, None) == aes.AES_EINVAL
+    assert enc(rk, 10, M, 4, A + 1024, 16, A, 4096, None, None) == aes.AES_EINVAL
+    assert "overlap" in aes.aes_last_error()
+    encv = lib.aes_cbc_encrypt_msgs_variant
+    for v in (dict(bpt=3), dict(bpt=aes.AES_BPT_COLUMN), dict(placement=aes.AES_PLACEMENT_BITSLICED, wg=256),
+              dict(wg=96), dict(grid=-1)):
+        assert encv(rk, 10, M, 4, A, 64, B, 64, None, var(**v), None) == aes.AES_EINVAL, v
+    assert encv(rk, 10, M, 4, A, 64, B, 64, None, None, None) == aes.AES_EINVAL  # null variant
+
+
+def test_cbc_msg_record_layout():
+    # the numpy record the binding builds is the C struct aes_cbc_msg
+    assert aes.CBC_MSG_DTYPE.itemsize == 48
+    assert [aes.CBC_MSG_DTYPE.fields[f][1] for f in ("in_block", "out_block", "nblocks", "reserved", "iv")] == \
+        [0, 8, 16, 24, 32]
+
+
 def test_pipe_config_checks_before_any_device_call():
     lib = aes._lib()
     aes._pipe_sigs(lib)
