@@ -191,9 +191,10 @@ int aes_cbc_decrypt_variant(const uint32_t *rk, int nr, const uint8_t *iv, const
  *              message's output is left untouched.
  *   nmsgs:     0 is a no-op returning AES_OK.
  * One chain has one block in flight, so a launch keeps every compute unit
- * busy only with about 2^18 messages or more; fewer are bound by the latency
- * of a block's rounds.  The 64 consecutive entries that one wave walks take
- * as long as the longest of them: list messages of similar length together.
+ * busy only with about 2^17 messages or more; fewer are bound by the latency
+ * of a block's rounds.  The consecutive entries that one wave walks (64, or
+ * 16 for short lists) take as long as the longest of them: list messages of
+ * similar length together.
  * Asynchronous on stream.
  */
 typedef struct {
@@ -206,11 +207,15 @@ typedef struct {
 int aes_cbc_encrypt_msgs(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs, const void *in_base,
                          size_t in_blocks, void *out_base, size_t out_blocks, uint32_t *rejected_dev, void *stream);
 /* Same with an explicit variant: bpt = blocks a lane loads and stores at once
- * (1, 2, 4 or 8), wg, a table placement (not bitsliced), grid (0 = as many
- * workgroups as fit on every compute unit, no more than the messages need).
- * AES_EINVAL outside that.  aes_cbc_encrypt_msgs takes bpt 8, the 4-table
- * placement and the smallest workgroup (up to 1024 threads) that gives every
- * compute unit the same number of 64-message waves. */
+ * (1, 2, 4 or 8; one lane walks one message), or AES_BPT_COLUMN (four lanes
+ * share a message, one column word each, 16 messages per wave: shorter
+ * rounds for short lists); wg, a table placement (not bitsliced), grid (0 =
+ * as many workgroups as fit on every compute unit, no more than the messages
+ * need).  AES_EINVAL outside that.  aes_cbc_encrypt_msgs takes the 4-table
+ * placement, bpt 8 when there are at least 8 one-lane waves per compute unit
+ * (2^17 messages on 256 CUs) and AES_BPT_COLUMN below that, and the smallest
+ * workgroup (up to 1024 threads) that gives every compute unit the same
+ * number of waves. */
 int aes_cbc_encrypt_msgs_variant(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs,
                                  const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
                                  uint32_t *rejected_dev, const aes_variant *variant, void *stream);

@@ -274,17 +274,22 @@ int run_cbc_decrypt(const uint32_t* rk, int nr, const uint8_t* iv, const void* i
     return AES_OK;
 }
 
-// Shape of aes_cbc_encrypt_msgs when the caller names none: 8 blocks (one
-// 128-byte line) per lane per load and store and the 4-table placement (one
-// workgroup per CU), with workgroups just large enough to give every CU the
-// same number of 64-message waves, up to 1024 threads: a smaller message
-// list then still spreads over all CUs instead of filling a few.
+// Shape of aes_cbc_encrypt_msgs when the caller names none, on the 4-table
+// placement (one workgroup per CU).  With at least 8 one-lane-per-message
+// waves per CU (64 messages each) the lanes walk whole states, 8 blocks (one
+// 128-byte line) per load and store; with fewer, a block's rounds are the
+// bound and four lanes share a message (AES_BPT_COLUMN, 16 messages per
+// wave), which shortens them.  Workgroups are just large enough to give
+// every CU the same number of waves, up to 1024 threads, so a short list
+// still spreads over all CUs instead of filling a few.
 aes_variant cbc_msgs_default(size_t nmsgs, int cus)
 {
-    const uint64_t units = (nmsgs + 63u) / 64u;
-    const uint64_t per_cu = cus > 0 ? (units + (uint64_t)cus - 1) / (uint64_t)cus : 16u;
+    const uint64_t c = cus > 0 ? (uint64_t)cus : 256u;
+    const bool quads = (nmsgs + 63u) / 64u < 8u * c;
+    const uint64_t waves = quads ? (nmsgs + 15u) / 16u : (nmsgs + 63u) / 64u;
+    const uint64_t per_cu = (waves + c - 1) / c;
     const int wg = (int)std::min<uint64_t>(1024u, 64u * std::max<uint64_t>(per_cu, 1u));
-    return aes_variant{8, wg, AES_PLACEMENT_TTABLE4, 0};
+    return aes_variant{quads ? AES_BPT_COLUMN : 8, wg, AES_PLACEMENT_TTABLE4, 0};
 }
 
 // v == nullptr: the default shape for this many messages (cbc_msgs_default).
@@ -314,8 +319,9 @@ int run_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev
     if (ib != ob && ib < ob + (uint64_t)out_blocks * 16u && ob < ib + (uint64_t)in_blocks * 16u)
         return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
     if (v != nullptr) {
-        if (v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != 8)
-            return fail(AES_EINVAL, "bpt (blocks a lane loads at once) must be 1, 2, 4 or 8, got %d", v->bpt);
+        if (v->bpt != AES_BPT_COLUMN && v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != 8)
+            return fail(AES_EINVAL,
+                        "bpt (blocks a lane loads at once) must be 1, 2, 4 or 8, or AES_BPT_COLUMN, got %d", v->bpt);
         aes_variant shape_only = *v;
         shape_only.bpt = 1;
         int rc = check_variant(&shape_only);

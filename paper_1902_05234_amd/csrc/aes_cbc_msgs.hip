@@ -20,7 +20,15 @@
 // (16 per CU with the 4-table placement: 2^18 messages on 256 CUs); with
 // fewer messages a launch is bound by the latency of one block's rounds.  A
 // wave lasts as long as the longest of its 64 messages.
+//
+// For that latency-bound regime a second kernel gives each message a quad of
+// lanes, one column word per lane (the round of aes_col_round.hpp: four
+// lookups per lane per round and three quad exchanges), 16 messages per
+// wave: a block's rounds take about half as long, at some more VALU work per
+// block (2^16 messages of 16 KiB: 1172 against 847 GB/s; from 2^17 messages
+// on the one-lane kernel is faster).
 #include "aes_cbc_msgs.hpp"
+#include "aes_col_round.hpp"
 #include "aes_ecb_kernel.hpp"
 
 namespace aesgpu {
@@ -48,6 +56,14 @@ __device__ __forceinline__ void load_group(uint4 (&v)[G], const uint4* src, uint
             v[k] = src[first + k];
 }
 
+// Message ranges inside their arenas (written so that no sum can wrap) and
+// the reserved field zero.
+__device__ __forceinline__ bool msg_ok(const CbcMsg& d, uint64_t in_blocks, uint64_t out_blocks)
+{
+    return d.reserved == 0 && d.in_block <= in_blocks && d.nblocks <= in_blocks - d.in_block &&
+           d.out_block <= out_blocks && d.nblocks <= out_blocks - d.out_block;
+}
+
 template <int NR, int G, int PL>
 __global__ __launch_bounds__(1024) void cbc_enc_msgs_kernel(const CbcMsg* __restrict__ msgs, uint64_t nmsgs,
                                                             const uint4* in, uint64_t in_blocks, uint4* out,
@@ -71,10 +87,7 @@ __global__ __launch_bounds__(1024) void cbc_enc_msgs_kernel(const CbcMsg* __rest
         uint4 chain = make_uint4(0u, 0u, 0u, 0u);
         if (m < nmsgs) {
             const CbcMsg d = msgs[m];
-            // both ranges inside their arenas, written so that no sum can wrap
-            const bool ok = d.reserved == 0 && d.in_block <= in_blocks && d.nblocks <= in_blocks - d.in_block &&
-                            d.out_block <= out_blocks && d.nblocks <= out_blocks - d.out_block;
-            if (ok) {
+            if (msg_ok(d, in_blocks, out_blocks)) {
                 nb = d.nblocks;
                 src = in + d.in_block;
                 dst = out + d.out_block;
@@ -108,6 +121,104 @@ __global__ __launch_bounds__(1024) void cbc_enc_msgs_kernel(const CbcMsg* __rest
     }
 }
 
+// One message per quad: lane 4q + j walks column word j of message 16u + q,
+// loading and storing word j of kColGroup blocks (one 128-byte line per
+// message) at a time.
+constexpr int kColGroup = 8;
+
+template <int NR, int PL>
+__global__ __launch_bounds__(1024) void cbc_enc_msgs_col_kernel(const CbcMsg* __restrict__ msgs, uint64_t nmsgs,
+                                                                const uint32_t* in, uint64_t in_blocks,
+                                                                uint32_t* out, uint64_t out_blocks,
+                                                                uint32_t* rejected, RoundKeys rk)
+{
+    __shared__ __align__(16) uint32_t lds[Layout<PL, false>::words];
+    fill_tables<PL, false>(lds, &c_tables);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t j = lane & 3u;
+    uint32_t kc[NR + 1];
+#pragma unroll
+    for (int r = 0; r <= NR; ++r)
+        kc[r] = j == 0 ? rk.w[4 * r] : j == 1 ? rk.w[4 * r + 1] : j == 2 ? rk.w[4 * r + 2] : rk.w[4 * r + 3];
+    __syncthreads();
+    const LaneBases<PL, false> lb(threadIdx.x);
+
+    const uint64_t waves_per_grid = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t units = (nmsgs + 15u) / 16u;
+    for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv < units;
+         wv += waves_per_grid) {
+        const uint64_t m = wv * 16u + (lane >> 2);
+        uint64_t nb = 0;
+        const uint32_t* src = in;
+        uint32_t* dst = out;
+        uint32_t chain = 0;
+        if (m < nmsgs) {
+            const CbcMsg d = msgs[m];  // the four lanes of a quad read the same record
+            if (msg_ok(d, in_blocks, out_blocks)) {
+                nb = d.nblocks;
+                src = in + 4u * d.in_block + j;
+                dst = out + 4u * d.out_block + j;
+                chain = j == 0 ? d.iv.x : j == 1 ? d.iv.y : j == 2 ? d.iv.z : d.iv.w;
+            } else if (rejected != nullptr && j == 0) {
+                atomicAdd(rejected, 1u);
+            }
+        }
+        // a quad's lanes share nb, so a quad is wholly active or wholly idle
+        uint32_t cur[kColGroup];
+#pragma unroll
+        for (int k = 0; k < kColGroup; ++k)
+            if ((uint64_t)k < nb)
+                cur[k] = src[4u * k];
+        for (uint64_t g = 0; g < nb; g += kColGroup) {
+            uint32_t nxt[kColGroup];
+#pragma unroll
+            for (int k = 0; k < kColGroup; ++k)
+                if (g + kColGroup + k < nb)
+                    nxt[k] = src[4u * (g + kColGroup + k)];
+#pragma unroll
+            for (int k = 0; k < kColGroup; ++k) {
+                if (k == 0 || g + k < nb) {
+                    chain = col_block<NR, false, PL>(cur[k] ^ chain, lds, lb, kc);
+                    cur[k] = chain;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kColGroup; ++k)
+                if (k == 0 || g + k < nb)
+                    dst[4u * (g + k)] = cur[k];
+#pragma unroll
+            for (int k = 0; k < kColGroup; ++k)
+                cur[k] = nxt[k];
+        }
+    }
+}
+
+template <int NR, int PL>
+hipError_t launch_one_cbc_msgs_col(const CbcMsg* msgs, uint64_t nmsgs, const void* in, uint64_t in_blocks, void* out,
+                                   uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk,
+                                   const LaunchShape& shape, int cus, hipStream_t stream)
+{
+    auto kern = cbc_enc_msgs_col_kernel<NR, PL>;
+    int grid = shape.grid;
+    if (grid <= 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                                    shape.wg, 0);
+        if (e != hipSuccess)
+            return e;
+        grid = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    // no more workgroups than the 16-message wave units can keep busy
+    const uint64_t waves = (nmsgs + 15u) / 16u;
+    const uint64_t per_group = (uint64_t)shape.wg / 64u;
+    const uint64_t needed = (waves + per_group - 1) / per_group;
+    if ((uint64_t)grid > needed)
+        grid = (int)needed;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(shape.wg), 0, stream, msgs, nmsgs, static_cast<const uint32_t*>(in),
+                       in_blocks, static_cast<uint32_t*>(out), out_blocks, rejected, rk);
+    return hipGetLastError();
+}
+
 template <int NR, int G, int PL>
 hipError_t launch_one_cbc_msgs(const CbcMsg* msgs, uint64_t nmsgs, const void* in, uint64_t in_blocks, void* out,
                                uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk, const LaunchShape& shape,
@@ -139,11 +250,20 @@ hipError_t launch_cbc_msgs_nr(int nr, const CbcMsg* msgs, uint64_t nmsgs, const 
                               void* out, uint64_t out_blocks, uint32_t* rejected, const RoundKeys& rk,
                               const LaunchShape& shape, int cus, hipStream_t stream)
 {
-    switch (nr) {
-    case 10: return launch_one_cbc_msgs<10, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
-    case 12: return launch_one_cbc_msgs<12, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
-    case 14: return launch_one_cbc_msgs<14, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
-    default: return hipErrorInvalidValue;
+    if constexpr (G == 0) {  // one column per lane (AES_BPT_COLUMN)
+        switch (nr) {
+        case 10: return launch_one_cbc_msgs_col<10, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        case 12: return launch_one_cbc_msgs_col<12, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        case 14: return launch_one_cbc_msgs_col<14, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (nr) {
+        case 10: return launch_one_cbc_msgs<10, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        case 12: return launch_one_cbc_msgs<12, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        case 14: return launch_one_cbc_msgs<14, G, PL>(msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
+        default: return hipErrorInvalidValue;
+        }
     }
 }
 
@@ -153,6 +273,7 @@ hipError_t launch_cbc_msgs_g(int nr, const CbcMsg* msgs, uint64_t nmsgs, const v
                              const LaunchShape& shape, int cus, hipStream_t stream)
 {
     switch (shape.bpt) {
+    case 0: return launch_cbc_msgs_nr<0, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
     case 1: return launch_cbc_msgs_nr<1, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
     case 2: return launch_cbc_msgs_nr<2, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);
     case 4: return launch_cbc_msgs_nr<4, PL>(nr, msgs, nmsgs, in, in_blocks, out, out_blocks, rejected, rk, shape, cus, stream);

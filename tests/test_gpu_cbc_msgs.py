@@ -65,7 +65,7 @@ def test_ragged_message_set_matches_oracle(oracle_lib, keybits):
     untouched_outside(recs, got, "%d-bit" % keybits)
 
 
-VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=3) for p in (0, 1, 2) for b in (1, 2, 4, 8)
+VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=3) for p in (0, 1, 2) for b in (aes.AES_BPT_COLUMN, 1, 2, 4, 8)
             for w in (64, 1024)]
 
 

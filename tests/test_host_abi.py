@@ -286,8 +286,8 @@ def test_cbc_encrypt_msgs_argument_checks_before_any_device_call():
     assert enc(rk, 10, M, 4, A + 1024, 16, A, 4096, None, None) == aes.AES_EINVAL
     assert "overlap" in aes.aes_last_error()
     encv = lib.aes_cbc_encrypt_msgs_variant
-    for v in (dict(bpt=3), dict(bpt=aes.AES_BPT_COLUMN), dict(placement=aes.AES_PLACEMENT_BITSLICED, wg=256),
-              dict(wg=96), dict(grid=-1)):
+    for v in (dict(bpt=3), dict(bpt=16), dict(placement=aes.AES_PLACEMENT_BITSLICED, wg=256), dict(wg=96),
+              dict(grid=-1)):
         assert encv(rk, 10, M, 4, A, 64, B, 64, None, var(**v), None) == aes.AES_EINVAL, v
     assert encv(rk, 10, M, 4, A, 64, B, 64, None, None, None) == aes.AES_EINVAL  # null variant
 
