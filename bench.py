@@ -873,7 +873,8 @@ def main():
                          "bitsliced kernel beside the 4-table kernel on two streams, 30 steps (for a kernel "
                          "trace); corun-sweep: their sustained rates over bitsliced shares 0 ... 0.24; ctr: 1 GiB CTR and ECB "
                          "encryptions in turn (for counters); cbc-msgs: 3 copies of 1 GiB, then CBC encryption of 1 GiB as "
-                         "2^18 messages of 4 KiB and ECB encryption of the same buffer, in turn (for counters); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
+                         "2^18 messages of 4 KiB and ECB encryption of the same buffer, in turn, then CBC encryption "
+                         "of 1 GiB as 2^16 messages of 16 KiB (for counters and traces); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
                          "and the bitsliced kernel at 1 GiB (for counters); host: the host-inclusive file-size sweep "
                          "only (for a kernel and copy trace)")
     args = ap.parse_args()
@@ -940,11 +941,17 @@ def main():
         ks = aes.aes_expand_key(inputs.random_key(1, 128))
         nm = GiB // 4096
         msgs = torch.from_numpy(cbc_records(inputs.cbc_equal_messages(3, nm, 256)).view(np.uint8)).to("cuda")
+        # and 1 GiB as 2^16 messages of 16 KiB, which the default runs four
+        # lanes per message
+        nq = GiB // 16384
+        msgs_q = torch.from_numpy(cbc_records(inputs.cbc_equal_messages(4, nq, 1024)).view(np.uint8)).to("cuda")
         for _ in range(3):
             aes.aes_device_copy(x, y)  # known bytes: the counters' calibration
         for _ in range(max(1, args.steps)):
             aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, nm, x, y)
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
+        for _ in range(max(1, args.steps)):
+            aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs_q, nq, x, y)
         torch.cuda.synchronize()
         log("cbc-msgs profile launches done")
         return
