@@ -3,9 +3,10 @@ eq 2 read with the block cipher; one chain per message) against the CPU
 oracle's sequential CBC encryption, bit-exact: ragged message sets (empty
 and one-block messages, lengths that are not a multiple of a lane's load
 group, gaps and a shuffled output order) for every key size, every kernel
-variant with a small grid so waves take several 64-message units, in-place
-messages, a message continued across two launches, messages the kernel must
-skip, and the 1 GiB set of 2^18 four-KiB messages on sampled messages."""
+variant with a small grid so waves take several wave units, both kernels
+on every table placement for 192- and 256-bit keys, in-place messages, a
+message continued across two launches, messages the kernel must skip, and
+the 1 GiB set of 2^18 four-KiB messages on sampled messages."""
 import numpy as np
 import pytest
 
@@ -84,6 +85,26 @@ def test_every_variant_matches_oracle(oracle_lib, variant):
     got = to_host(out)
     check_messages(oracle_lib, key, recs, src, got, str(variant))
     untouched_outside(recs, got, str(variant))
+
+
+@pytest.mark.parametrize("keybits", [192, 256])
+@pytest.mark.parametrize("placement", [0, 1, 2])
+@pytest.mark.parametrize("bpt", [aes.AES_BPT_COLUMN, 8], ids=["quads", "lanes"])
+def test_both_kernels_every_placement_for_longer_keys(oracle_lib, keybits, placement, bpt):
+    # the 2-table placement takes inner round keys turned right by 8 bits,
+    # which the longer schedules exercise over more rounds
+    torch = cuda()
+    ms = inputs.cbc_message_set(880 + keybits + placement, 300, 40)
+    key = inputs.random_key(881 + placement, keybits)
+    ks = aes.aes_expand_key(key)
+    src = inputs.random_bytes(882 + keybits, 16 * ms.in_blocks)
+    out = torch.full((16 * ms.out_blocks,), SENTINEL, dtype=torch.uint8, device="cuda")
+    recs = records(ms)
+    v = aes.Variant(bpt=bpt, wg=256, placement=placement)
+    run(ks, recs, to_dev(src), out, variant=v)
+    got = to_host(out)
+    check_messages(oracle_lib, key, recs, src, got, "%d-bit %s" % (keybits, v))
+    untouched_outside(recs, got, "%d-bit %s" % (keybits, v))
 
 
 def test_in_place_messages(oracle_lib):
