@@ -370,10 +370,11 @@ class RecordMismatch(RuntimeError):
     """A tuning record made on another device or for other kernel sources."""
 
 
-def record_mismatch(record: dict, device=None, arch=None, src_hash=None):
-    """Reasons the record does not describe this device and these kernels
-    (empty when it does).  device/arch: the current device's name and
-    architecture (None: not checked); src_hash: defaults to source_hash()."""
+def record_mismatch(record: dict, device=None, arch=None, src_hash=None, hip=None):
+    """Reasons the record does not describe this device, runtime and these
+    kernels (empty when it does).  device/arch: the current device's name and
+    architecture; hip: the HIP runtime version the timings ran under (None:
+    not checked); src_hash: defaults to source_hash()."""
     why = []
     want = source_hash() if src_hash is None else src_hash
     if record.get("source_hash") != want:
@@ -382,6 +383,8 @@ def record_mismatch(record: dict, device=None, arch=None, src_hash=None):
         why.append("made on device %r, this is %r" % (record.get("device"), device))
     if arch is not None and record.get("arch") is not None and record.get("arch") != arch:
         why.append("made for architecture %r, this is %r" % (record.get("arch"), arch))
+    if hip is not None and record.get("hip") is not None and record.get("hip") != hip:
+        why.append("timed under HIP runtime %s, this is %s" % (record.get("hip"), hip))
     return why
 
 
@@ -399,14 +402,17 @@ def winners(record: dict):
 
 def apply(record: dict, force: bool = False):
     """Install the plain-path winners of a record into the library's tuning
-    table.  A record made on another device or architecture, or for other
-    kernel sources, is refused (RecordMismatch) unless ``force``."""
+    table.  A record made on another device or architecture, under another
+    HIP runtime, or for other kernel sources, is refused (RecordMismatch)
+    unless ``force``."""
     if not force:
         try:
-            name, arch = device_identity()
+            import torch
+            name, arch = device_identity(torch)
+            hip = torch.version.hip
         except Exception:  # no device to compare with: only the sources are checked
-            name = arch = None
-        why = record_mismatch(record, name, arch)
+            name = arch = hip = None
+        why = record_mismatch(record, name, arch, hip=hip)
         if why:
             raise RecordMismatch("tuning record refused (%s); pass force=True to install it anyway" % "; ".join(why))
     n = 0

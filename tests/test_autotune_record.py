@@ -56,12 +56,12 @@ def test_record_has_a_batch_winner_from_the_full_search():
 
 
 def test_record_mismatch_names_every_difference():
-    rec = {"source_hash": "aaaa", "device": "dev A", "arch": "gfx950:sramecc+:xnack-"}
-    assert autotune.record_mismatch(rec, "dev A", "gfx950:sramecc+:xnack-", src_hash="aaaa") == []
-    why = autotune.record_mismatch(rec, "dev B", "gfx942", src_hash="bbbb")
-    assert len(why) == 3
+    rec = {"source_hash": "aaaa", "device": "dev A", "arch": "gfx950:sramecc+:xnack-", "hip": "7.0.1"}
+    assert autotune.record_mismatch(rec, "dev A", "gfx950:sramecc+:xnack-", src_hash="aaaa", hip="7.0.1") == []
+    why = autotune.record_mismatch(rec, "dev B", "gfx942", src_hash="bbbb", hip="6.4.0")
+    assert len(why) == 4
     assert any("kernel sources" in w for w in why) and any("device" in w for w in why)
-    assert any("architecture" in w for w in why)
+    assert any("architecture" in w for w in why) and any("HIP runtime" in w for w in why)
     # no device to compare with: only the sources are checked
     assert autotune.record_mismatch(rec, None, None, src_hash="aaaa") == []
 
