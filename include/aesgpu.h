@@ -259,8 +259,10 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  *                           run passes AES_PIPE_HOST_PINNED.
  *   chunk_bytes:            positive multiple of 16.
  *   nslots:                 1..AES_PIPE_MAX_SLOTS streams (chunks in flight).
- * aes_pipe_create records the current device and creates the streams and
- * events; aes_pipe_destroy waits for them and frees them (not the memory).
+ * aes_pipe_create records the current device and creates the streams, the
+ * events and one 256-byte page of pinned host memory (hipHostMalloc) that
+ * holds the single-launch path's completion word; aes_pipe_destroy waits for
+ * the streams and frees all three (not the caller's memory).
  *
  * aes_pipe_run(p, op, rk, nr, iv, host_in, host_out, nbytes, flags):
  *   op:      AES_PIPE_ECB_ENCRYPT / AES_PIPE_ECB_DECRYPT (rk = rk_enc /
@@ -275,6 +277,9 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  * host memory when the device maps it (the caller's pinned buffers, or the
  * pipe's pinned staging): each range must lie inside one page-locked
  * allocation mapped at the same address; otherwise it takes the copy path.
+ * That launch is followed by a one-thread kernel that writes a completion
+ * word into the pipe's pinned page, which the call polls (falling back to
+ * the runtime's wait after 2 ms, or when the page could not be allocated).
  * Synchronous: returns when host_out holds the result.  Calls on one pipe
  * are serialised.  Errors: AES_EINVAL for bad arguments, AES_EHIP for a
  * failed copy or launch (all slots are drained before returning).

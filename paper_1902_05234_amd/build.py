@@ -22,9 +22,9 @@ LIBRARY = os.path.join(HERE, "libaesgpu.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 ARCH = os.environ.get("AESGPU_ARCH", "gfx950")
-SOURCES = ["aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip", "aes_ecb_col.hip", "aes_ecb.hip", "aes_ctr.hip", "aes_cbc.hip", "aes_cbc_msgs.hip", "aes_bitslice.hip", "aes_microbench.hip", "aes_batch.hip", "aes_abi.cpp", "aes_serve.cpp", "aes_pipe.cpp"]
+SOURCES = ["aes_ecb_p4.hip", "aes_ecb_p2.hip", "aes_ecb_p1.hip", "aes_ecb_col.hip", "aes_ecb.hip", "aes_ctr.hip", "aes_cbc.hip", "aes_cbc_msgs.hip", "aes_host_word.hip", "aes_bitslice.hip", "aes_microbench.hip", "aes_batch.hip", "aes_abi.cpp", "aes_serve.cpp", "aes_pipe.cpp"]
 HEADERS = ["aes_sbox_circuit.hpp", "aes_device.hpp", "aes_ecb_kernel.hpp", "aes_internal.hpp", "aes_tables.hpp",
-           "aes_batch_signal.hpp", "aes_cbc_msgs.hpp", "aes_col_round.hpp", "aes_tune_defaults.inc"]
+           "aes_batch_signal.hpp", "aes_cbc_msgs.hpp", "aes_col_round.hpp", "aes_host_word.hpp", "aes_tune_defaults.inc"]
 
 # Packed-FP32 instruction forms stay off for every GPU compile.
 COMMON = [

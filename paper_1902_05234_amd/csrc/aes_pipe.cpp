@@ -12,7 +12,8 @@
 // through the slot's pinned chunk (a CPU copy on each side); buffers the
 // caller allocated pinned (AES_PIPE_HOST_PINNED) are copied directly.  The
 // caller provides the device workspace and the pinned staging; the pipe
-// creates only streams and events.
+// creates its streams and events and one small pinned page for a completion
+// word.
 //
 // A buffer of at most one chunk (and kDirectMax) skips the copies over the
 // host link: the kernel runs on host memory the device maps, the caller's
@@ -21,10 +22,16 @@
 // from 1 KB to 150 KB).  A host range qualifies only if it lies inside one
 // page-locked allocation that the device maps at the same address
 // (hipPointerGetAttributes, hipMemGetAddressRange); anything else takes the
-// copy path.
+// copy path.  The direct path learns that its launch finished from a word
+// that a one-thread kernel behind it writes into a pinned page of the pipe
+// (aes_host_word.hip), which the calling thread polls: the runtime's own
+// completion wait arrives about 5 us later.  A launch not seen finished
+// within kWordWaitSeconds is waited for through the runtime, which also
+// reports a failed kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 
 #include <cstdint>
 #include <cstring>
@@ -33,6 +40,7 @@
 #include <vector>
 
 #include "../../include/aesgpu.h"
+#include "aes_host_word.hpp"
 #include "aes_internal.hpp"
 
 namespace aesgpu {
@@ -56,6 +64,9 @@ struct aes_pipe {
     uint64_t chunk = 0;
     bool has_pinned = false;
     bool staging_mapped = false;  // the pinned staging is addressable by the kernels
+    uint32_t* word = nullptr;     // pinned page of the pipe: the direct path's completion word
+    uint32_t* word_dev = nullptr; // its device address
+    uint32_t seq = 0;             // last value a completion kernel was asked to store
     std::vector<aesgpu::Slot> slots;
     std::mutex mu;  // one run at a time per pipe
 };
@@ -99,6 +110,27 @@ void destroy_slots(aes_pipe* p)
             hipStreamDestroy(s.stream);
     }
     p->slots.clear();
+    if (p->word != nullptr)
+        hipHostFree(p->word);
+    p->word = p->word_dev = nullptr;
+}
+
+// Longest the direct path polls its completion word before it waits through
+// the runtime (a kernel that failed never writes the word).
+constexpr double kWordWaitSeconds = 2e-3;
+
+// Wait for the work enqueued on `stream` up to and including a completion
+// kernel that stores `seq` into *word: poll the word, then the runtime.
+hipError_t wait_word(const volatile uint32_t* word, uint32_t seq, hipStream_t stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t spins = 1;; ++spins) {
+        if (__atomic_load_n(const_cast<const uint32_t*>(word), __ATOMIC_ACQUIRE) == seq)
+            return hipSuccess;
+        if ((spins & 1023u) == 0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > kWordWaitSeconds)
+            return hipStreamSynchronize(stream);
+    }
 }
 
 bool overlap_partial(const void* a, const void* b, uint64_t n)
@@ -200,6 +232,19 @@ static int pipe_create(const aes_pipe_config* cfg, aes_pipe** out)
             return fail_hip(e, "pipe: stream or event creation");
         }
     }
+    // the completion word: without a mapped page the direct path waits on an event
+    void* page = nullptr;
+    if (hipHostMalloc(&page, 256, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+        void* dev = nullptr;
+        if (hipHostGetDevicePointer(&dev, page, 0) == hipSuccess && dev != nullptr) {
+            p->word = static_cast<uint32_t*>(page);
+            p->word_dev = static_cast<uint32_t*>(dev);
+            __atomic_store_n(p->word, 0u, __ATOMIC_RELEASE);
+        } else {
+            hipHostFree(page);
+        }
+    }
+    (void)hipGetLastError();  // a refused page leaves no error for the next launch
     *out = p;
     return AES_OK;
 }
@@ -279,10 +324,16 @@ static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8
         if (kin != nullptr) {
             int rc = AES_OK;
             hipError_t e = launch_piece(op, nr, keys, c0, 0, kin, kout, nbytes, cus, s.stream);
-            if (e == hipSuccess)
+            if (e == hipSuccess && p->word != nullptr) {
+                const uint32_t seq = ++p->seq;
+                e = launch_host_word(p->word_dev, seq, s.stream);
+                if (e == hipSuccess)
+                    e = wait_word(p->word, seq, s.stream);
+            } else if (e == hipSuccess) {
                 e = hipEventRecord(s.event, s.stream);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(s.event);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(s.event);
+            }
             if (e != hipSuccess)
                 rc = fail_hip(e, "pipe: kernel on host memory");
             else if (staged)

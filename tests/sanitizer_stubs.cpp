@@ -7,6 +7,7 @@
 
 #include "aes_batch_signal.hpp"
 #include "aes_cbc_msgs.hpp"
+#include "aes_host_word.hpp"
 #include "aes_internal.hpp"
 
 namespace aesgpu {
@@ -44,6 +45,8 @@ hipError_t launch_cbc_encrypt_msgs(const LaunchShape&, int, int, const void*, ui
 {
     return hipErrorInvalidValue;
 }
+
+hipError_t launch_host_word(uint32_t*, uint32_t, hipStream_t) { return hipErrorInvalidValue; }
 
 hipError_t launch_batch(const BatchArgs&, int, int, int, int, hipStream_t) { return hipErrorInvalidValue; }
 

@@ -97,6 +97,42 @@ def test_pipe_pinned_small_buffers_run_on_host_memory(oracle_lib):
         p.close()
 
 
+def test_pipe_many_small_calls_in_a_row(oracle_lib):
+    """Back-to-back calls that take the single-launch path, pinned and staged,
+    ECB both ways and CTR, each result read as soon as its call returns: the
+    call must not return before the kernel's output is in host memory."""
+    torch = cuda()
+    key = inputs.random_key(818, 128)
+    ks = aes.aes_expand_key(key)
+    iv = bytes(range(16, 32))
+    p = aes.HostPipe(chunk_bytes=256 << 10, nslots=2)
+    try:
+        src = torch.zeros(256 << 10, dtype=torch.uint8).pin_memory()
+        dst = torch.zeros(256 << 10, dtype=torch.uint8).pin_memory()
+        g = inputs.rng(818)
+        for i in range(240):
+            n = int(g.integers(1, 4097)) * 16
+            x = inputs.random_bytes(900 + i, n)
+            kind = i % 4
+            if kind == 0:                                          # pinned, direct on the caller's buffers
+                src[:n].copy_(torch.from_numpy(x))
+                p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, src[:n], out=dst[:n])
+                got, want = dst[:n].numpy(), oracle_lib.ecb_encrypt(key, x)
+            elif kind == 1:                                        # pageable, through the staging
+                got, want = p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x), oracle_lib.ecb_encrypt(key, x)
+            elif kind == 2:
+                c = oracle_lib.ecb_encrypt(key, x)
+                got, want = p.run(aes.AES_PIPE_ECB_DECRYPT, ks, c), x
+            else:
+                m = n - int(g.integers(0, 16))
+                src[:m].copy_(torch.from_numpy(x[:m]))
+                p.run(aes.AES_PIPE_CTR, ks, src[:m], out=dst[:m], iv=iv)
+                got, want = dst[:m].numpy(), oracle_lib.ctr_crypt(key, iv, x[:m])
+            assert_same(got, want, "call %d (kind %d, %d bytes)" % (i, kind, n))
+    finally:
+        p.close()
+
+
 def test_pipe_pieces_smaller_than_the_chunk(oracle_lib):
     """With the default 2 x 32 MiB pipe a buffer of a few MiB is cut into
     1-2 MiB pieces (two per slot) so its copies still overlap: ECB and CTR
