@@ -16,9 +16,11 @@
  *     torch tensor's data_ptr()); "host pointer" = ordinary process memory.
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
  *     work is enqueued asynchronously on it; the call returns without waiting.
- *   - The caller owns every buffer.  No entry point allocates or frees device
- *     memory; the library's only state is its immutable tables (in the code
- *     object) and the tuning table set by aes_tune_set.
+ *   - The caller owns every buffer it passes.  No entry point allocates or
+ *     frees device memory.  Besides its immutable tables (in the code object)
+ *     and the tuning table set by aes_tune_set, the library holds only what a
+ *     pipe or server handle creates (streams, events, a worker thread, the
+ *     pipe's 256-byte pinned completion page), released by its destroy call.
  *   - A 16-byte block is processed byte-for-byte as FIPS-197's input array:
  *     byte r + 4c is state row r, column c.  No padding is applied: callers
  *     pass whole blocks.
