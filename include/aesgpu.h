@@ -17,8 +17,9 @@
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
  *     work is enqueued asynchronously on it; the call returns without waiting.
  *   - The caller owns every buffer it passes.  No entry point allocates or
- *     frees device memory.  Besides its immutable tables (in the code object)
- *     and the tuning table set by aes_tune_set, the library holds only what a
+ *     frees device memory.  Besides its immutable tables and the static
+ *     scratch array of aes_ecb_batch_noalloc (both in the code object) and
+ *     the tuning table set by aes_tune_set, the library holds only what a
  *     pipe or server handle creates (streams, events, a worker thread, the
  *     pipe's 256-byte pinned completion page), released by its destroy call.
  *   - A 16-byte block is processed byte-for-byte as FIPS-197's input array:
