@@ -18,8 +18,9 @@
 // A buffer of at most one chunk (and kDirectMax) skips the copies over the
 // host link: the kernel runs on host memory the device maps, the caller's
 // pinned buffers themselves (if 16-byte aligned) or the slot's pinned chunk.  That takes one
-// launch instead of two copies and a launch (about 19 us against 24-46 us
-// from 1 KB to 150 KB).  A host range qualifies only if it lies inside one
+// launch instead of two copies and a launch (from 1 KB to 150 KB about 19 us
+// against 24-46 us when both waited through the runtime).  A host range
+// qualifies only if it lies inside one
 // page-locked allocation that the device maps at the same address
 // (hipPointerGetAttributes, hipMemGetAddressRange); anything else takes the
 // copy path.  The direct path learns that its launch finished from a word
