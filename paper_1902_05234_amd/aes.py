@@ -352,6 +352,12 @@ def aes_size_bucket(nblocks: int) -> int:
     return int(_lib().aes_size_bucket(int(nblocks)))
 
 
+def expand_key(key: bytes) -> KeySchedule:
+    """Key schedule of a 16-, 24- or 32-byte key (encryption and equivalent
+    inverse), for ecb_encrypt / ecb_decrypt / ctr_crypt / cbc_decrypt."""
+    return aes_expand_key(key)
+
+
 def ecb_encrypt(ks: KeySchedule, x, out=None, stream=None):
     """Encrypt a uint8 CUDA tensor of whole blocks; returns ``out``."""
     import torch

@@ -60,6 +60,8 @@ def test_encryption_schedule_matches_oracle(oracle_lib, keybits):
         w, nr = oracle_lib.expand_key(key)
         assert ks.nr == nr
         assert np.array_equal(ks.rk_enc, le_words(w))
+        ks2 = aes.expand_key(key)  # the short name gives the same schedule
+        assert ks2.nr == nr and np.array_equal(ks2.rk_enc, ks.rk_enc) and np.array_equal(ks2.rk_dec, ks.rk_dec)
 
 
 @pytest.mark.parametrize("keybits", [128, 192, 256])
