@@ -282,7 +282,9 @@ int aes_roof_probe(int which, uint32_t iters, void *out_dev, size_t out_bytes, u
  * allocation mapped at the same address; otherwise it takes the copy path.
  * That launch is followed by a one-thread kernel that writes a completion
  * word into the pipe's pinned page, which the call polls (falling back to
- * the runtime's wait after 2 ms, or when the page could not be allocated).
+ * the runtime's wait after 2 ms, or when the page could not be allocated);
+ * a pageable buffer of 512 KiB or more goes through the staging in up to
+ * four pieces, so the CPU copies of one overlap the kernel of another.
  * Synchronous: returns when host_out holds the result.  Calls on one pipe
  * are serialised.  Errors: AES_EINVAL for bad arguments, AES_EHIP for a
  * failed copy or launch (all slots are drained before returning).

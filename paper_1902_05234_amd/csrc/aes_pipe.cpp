@@ -28,7 +28,9 @@
 // (aes_host_word.hip), which the calling thread polls: the runtime's own
 // completion wait arrives about 5 us later.  A launch not seen finished
 // within kWordWaitSeconds is waited for through the runtime, which also
-// reports a failed kernel.
+// reports a failed kernel.  A pageable buffer of 512 KiB or more on this path
+// goes through the staging in pieces (run_staged_pieces), so the CPU copies
+// of one piece overlap the kernel of another.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -121,12 +123,14 @@ void destroy_slots(aes_pipe* p)
 constexpr double kWordWaitSeconds = 2e-3;
 
 // Wait for the work enqueued on `stream` up to and including a completion
-// kernel that stores `seq` into *word: poll the word, then the runtime.
+// kernel that stores `seq` into *word: poll the word, then the runtime.  The
+// pipe's sequence numbers only grow (modulo 2^32) along the stream, so a
+// word at or past `seq` means that kernel has run.
 hipError_t wait_word(const volatile uint32_t* word, uint32_t seq, hipStream_t stream)
 {
     const auto t0 = std::chrono::steady_clock::now();
     for (uint32_t spins = 1;; ++spins) {
-        if (__atomic_load_n(const_cast<const uint32_t*>(word), __ATOMIC_ACQUIRE) == seq)
+        if (static_cast<int32_t>(__atomic_load_n(const_cast<const uint32_t*>(word), __ATOMIC_ACQUIRE) - seq) >= 0)
             return hipSuccess;
         if ((spins & 1023u) == 0 &&
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > kWordWaitSeconds)
@@ -166,6 +170,47 @@ hipError_t launch_piece(int op, int nr, const RoundKeys& keys, const Counter128&
         return launch_ctr(shape, v.placement, nr, in, out, len, c, keys, cus, stream);
     }
     return launch_ecb(shape, v.placement, nr, op == AES_PIPE_ECB_DECRYPT, in, out, blocks, keys, cus, stream);
+}
+
+// A staged single-launch buffer is cut into pieces of at least kStagedPiece
+// bytes (at most kStagedPieces of them): each is copied into the staging,
+// run there, and copied out as soon as its completion word arrives, so the
+// CPU copies of one piece overlap the kernel of another.
+constexpr uint64_t kStagedPiece = 256u << 10;
+constexpr uint64_t kStagedPieces = 4;
+
+hipError_t run_staged_pieces(aes_pipe* p, Slot& s, int op, int nr, const RoundKeys& keys, const Counter128& c0,
+                             const uint8_t* src, uint8_t* dst, uint64_t nbytes, int cus)
+{
+    const uint64_t np = std::min<uint64_t>(kStagedPieces, std::max<uint64_t>(1, nbytes / kStagedPiece));
+    const uint64_t plen = ((nbytes + np - 1) / np + 15u) & ~(uint64_t)15u;  // whole blocks: CTR pieces stay aligned
+    const uint32_t base = p->seq;
+    uint64_t launched = 0, done = 0;
+    auto len_of = [&](uint64_t i) { return std::min<uint64_t>(plen, nbytes - i * plen); };
+    auto finish_piece = [&](uint64_t i) {
+        hipError_t w = wait_word(p->word, base + (uint32_t)(i + 1), s.stream);
+        if (w == hipSuccess)
+            std::memcpy(dst + i * plen, s.pin + i * plen, len_of(i));
+        return w;
+    };
+    hipError_t e = hipSuccess;
+    for (uint64_t i = 0; i * plen < nbytes && e == hipSuccess; ++i) {
+        const uint64_t off = i * plen, len = len_of(i);
+        std::memcpy(s.pin + off, src + off, len);
+        e = launch_piece(op, nr, keys, c0, off, s.pin + off, s.pin + off, len, cus, s.stream);
+        if (e != hipSuccess)
+            break;
+        ++launched;  // in flight from here on: drained below if anything fails
+        e = launch_host_word(p->word_dev, ++p->seq, s.stream);
+        if (e == hipSuccess && i > 0 && (e = finish_piece(i - 1)) == hipSuccess)
+            ++done;
+    }
+    while (e == hipSuccess && done < launched)
+        if ((e = finish_piece(done)) == hipSuccess)
+            ++done;
+    if (e != hipSuccess && launched > 0)
+        (void)hipStreamSynchronize(s.stream);  // nothing of this call still runs on the staging
+    return e;
 }
 
 // copy the finished chunk of slot s from its pinned chunk to the caller's buffer
@@ -319,11 +364,19 @@ static int pipe_run(aes_pipe* p, int op, const uint32_t* rk, int nr, const uint8
             kin = host_in;
             kout = host_out;
         } else if (staged && p->staging_mapped) {
-            std::memcpy(s.pin, src, nbytes);
             kin = kout = s.pin;
+        }
+        if (kin != nullptr && staged && p->word != nullptr) {
+            hipError_t e = run_staged_pieces(p, s, op, nr, keys, c0, src, dst, nbytes, cus);
+            const int rc = e == hipSuccess ? AES_OK : fail_hip(e, "pipe: kernel on host memory");
+            if (prev_dev != p->device)
+                hipSetDevice(prev_dev);
+            return rc;
         }
         if (kin != nullptr) {
             int rc = AES_OK;
+            if (staged)
+                std::memcpy(s.pin, src, nbytes);
             hipError_t e = launch_piece(op, nr, keys, c0, 0, kin, kout, nbytes, cus, s.stream);
             if (e == hipSuccess && p->word != nullptr) {
                 const uint32_t seq = ++p->seq;

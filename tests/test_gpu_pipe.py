@@ -133,6 +133,33 @@ def test_pipe_many_small_calls_in_a_row(oracle_lib):
         p.close()
 
 
+def test_pipe_staged_buffers_in_pieces(oracle_lib):
+    """Pageable buffers up to 4 MiB go through the pinned staging in up to four
+    pieces, each copied in, run and copied out while the next one runs: sizes
+    around the piece boundaries, the largest single-launch buffer, CTR with a
+    partial last block across pieces, and in place."""
+    cuda()
+    key = inputs.random_key(825, 192)
+    ks = aes.aes_expand_key(key)
+    iv = bytes([0xff] * 8 + [0xfe] + [0xff] * 7)  # the counter's low half wraps inside the buffer
+    p = aes.HostPipe()  # 2 slots x 32 MiB: every size here takes the single-launch path
+    try:
+        for n in (256 << 10, (512 << 10) - 16, (512 << 10) + 16, 1190416, (3 << 20) + 48, 4 << 20):
+            x = inputs.random_bytes(826 + n, n)
+            c = p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, x)
+            assert_same(c, oracle_lib.ecb_encrypt(key, x), "staged enc n=%d" % n)
+            assert_same(p.run(aes.AES_PIPE_ECB_DECRYPT, ks, c), x, "staged dec n=%d" % n)
+        for m in (1000003, (4 << 20) - 5):
+            x = inputs.random_bytes(827 + m, m)
+            assert_same(p.run(aes.AES_PIPE_CTR, ks, x, iv=iv), oracle_lib.ctr_crypt(key, iv, x), "staged ctr n=%d" % m)
+        x = inputs.random_bytes(828, 2 << 20)
+        buf = x.copy()
+        p.run(aes.AES_PIPE_ECB_ENCRYPT, ks, buf, out=buf)                                   # in place
+        assert_same(buf, oracle_lib.ecb_encrypt(key, x), "staged enc in place")
+    finally:
+        p.close()
+
+
 def test_pipe_pieces_smaller_than_the_chunk(oracle_lib):
     """With the default 2 x 32 MiB pipe a buffer of a few MiB is cut into
     1-2 MiB pieces (two per slot) so its copies still overlap: ECB and CTR
