@@ -20,7 +20,8 @@ before timing starts.  Prints ONE JSON line:
   sweep        GB/s for every key size and direction, 1 MiB ... 4 GiB (device
                time: graph replays up to 64 MiB, event-timed launches above), plus
                an all-zero control, CTR and CBC decryption at 1 GiB, and CBC
-               encryption of 1 GiB as 2^18 independent 4 KiB messages
+               encryption and decryption of 1 GiB as 2^18 independent 4 KiB
+               messages
   host_path    the paper's file sizes (1,202 ... 1,190,402 bytes) host buffer
                in, host buffer out (host-link transfers included), pinned and
                pageable, beside the paper's own GPU times; and the 1 GiB
@@ -485,6 +486,8 @@ def sweep(torch, aes, inputs, sizes):
     msgs = torch.from_numpy(cbc_records(inputs.cbc_equal_messages(3, nm, 256)).view(np.uint8)).to("cuda")
     ms = timed10(lambda: aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, nm, xi, xo))
     out["aes128_cbc_enc_4KiB_msgs_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
+    ms = timed10(lambda: aes.aes_cbc_decrypt_msgs(ks.rk_dec, ks.nr, msgs, nm, xi, xo))
+    out["aes128_cbc_dec_4KiB_msgs_%s" % size_name(n)] = round(n / (ms * 1e-3) / 1e9, 1)
     del msgs
     # structured control, last because it overwrites the input: in an
     # all-zero buffer every block is the same, so every lane reads the same

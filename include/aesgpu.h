@@ -95,6 +95,9 @@ int aes_ecb_decrypt(const uint32_t *rk, int nr, const void *in, void *out, size_
  * lane issues four lookups per round instead of sixteen.  For launches bound
  * by the latency of one block's rounds (small buffers). */
 #define AES_BPT_COLUMN 0
+/* CBC message-set decryption with one wave per message:
+ * bpt = AES_BPT_WAVE_MSG + 1 or 2 (blocks per lane per 64-lane unit). */
+#define AES_BPT_WAVE_MSG 16
 typedef struct {
     int32_t bpt;       /* blocks per thread per iteration: 1, 2, 4 (16/32/64 bytes), or
                           AES_BPT_COLUMN: a quarter block, four lanes per block (ECB, table
@@ -220,6 +223,33 @@ int aes_cbc_encrypt_msgs(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev
  * workgroup (up to 1024 threads) that gives every compute unit the same
  * number of waves. */
 int aes_cbc_encrypt_msgs_variant(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs,
+                                 const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
+                                 uint32_t *rejected_dev, const aes_variant *variant, void *stream);
+
+/*
+ * aes_cbc_decrypt_msgs -- CBC decryption (section 3.1.2, eq 2 read as above:
+ * P_i = invcipher(C_i) XOR C_{i-1}, C_0 = iv) of the same kind of message
+ * set, under one key, in one launch: one message per lane, its blocks
+ * independent of each other, each XORed with the preceding ciphertext block.
+ *   rk:       host pointer to the DECRYPTION schedule (rk_dec), copied.
+ *   Other arguments, checks, skipped messages and errors as for
+ *   aes_cbc_encrypt_msgs; a message may run in place (equal ranges in one
+ *   arena).  For one long message aes_cbc_decrypt is the faster call (every
+ *   block of it in parallel); this call is for many messages at once.
+ * Two kernels: one message per lane (bpt = blocks a lane decrypts at once:
+ * 1, 2 or 4), for short messages, or one wave per message (bpt =
+ * AES_BPT_WAVE_MSG + 1 or 2 blocks per lane per 64-block unit, every
+ * access of the wave contiguous), for messages of 64 blocks or more.  The
+ * _variant form takes that bpt, wg, a table placement (not bitsliced) and
+ * grid.  The default uses 4 tables, one wave per message with 2 blocks per
+ * lane when the input arena averages at least 64 blocks per message (one
+ * lane per message with 4 otherwise), and the smallest workgroup (up to 1024
+ * threads) that gives every compute unit the same number of waves.
+ * Asynchronous on stream.
+ */
+int aes_cbc_decrypt_msgs(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs, const void *in_base,
+                         size_t in_blocks, void *out_base, size_t out_blocks, uint32_t *rejected_dev, void *stream);
+int aes_cbc_decrypt_msgs_variant(const uint32_t *rk, int nr, const aes_cbc_msg *msgs_dev, size_t nmsgs,
                                  const void *in_base, size_t in_blocks, void *out_base, size_t out_blocks,
                                  uint32_t *rejected_dev, const aes_variant *variant, void *stream);
 

@@ -23,6 +23,7 @@ TUNE_FORCE_ENV = "AESGPU_TUNE_FORCE"  # "1": install that record even if made on
 AES_OK, AES_EINVAL, AES_EALIGN, AES_ENOMEM, AES_EHIP, AES_EBUSY, AES_ERANGE = 0, -1, -2, -3, -4, -5, -6
 AES_PLACEMENT_TTABLE4, AES_PLACEMENT_TTABLE2, AES_PLACEMENT_TTABLE1, AES_PLACEMENT_BITSLICED = 0, 1, 2, 3
 AES_BPT_COLUMN = 0  # Variant.bpt: one column word per lane, four lanes per block
+AES_BPT_WAVE_MSG = 16  # Variant.bpt base of CBC message-set decryption with one wave per message
 AES_KEY_SLOT_WORDS, AES_KEY_SLOT_ENC, AES_KEY_SLOT_DEC, AES_KEY_SLOT_NR = 128, 0, 64, 124
 AES_SIZE_BUCKETS = 7
 
@@ -104,6 +105,9 @@ def _lib() -> ctypes.CDLL:
                 "aes_cbc_encrypt_msgs": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_p], _c_i),
                 "aes_cbc_encrypt_msgs_variant": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
                                                   ctypes.POINTER(_Variant), _c_p], _c_i),
+                "aes_cbc_decrypt_msgs": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_p], _c_i),
+                "aes_cbc_decrypt_msgs_variant": ([_u32p, _c_i, _c_p, _c_sz, _c_p, _c_sz, _c_p, _c_sz, _c_p,
+                                                  ctypes.POINTER(_Variant), _c_p], _c_i),
                 "aes_tune_set": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_tune_get": ([_c_i, _c_i, _c_sz, ctypes.POINTER(_Variant)], _c_i),
                 "aes_size_bucket": ([_c_sz], _c_i),
@@ -137,7 +141,8 @@ def exported_symbols():
     """Names this binding expects the library to export."""
     return ["aes_last_error", "aes_expand_key", "aes_key_slot", "aes_ecb_encrypt", "aes_ecb_decrypt",
             "aes_ecb_crypt_variant", "aes_ctr_crypt", "aes_ctr_crypt_variant", "aes_cbc_decrypt",
-            "aes_cbc_decrypt_variant", "aes_cbc_encrypt_msgs", "aes_cbc_encrypt_msgs_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
+            "aes_cbc_decrypt_variant", "aes_cbc_encrypt_msgs", "aes_cbc_encrypt_msgs_variant", "aes_cbc_decrypt_msgs",
+            "aes_cbc_decrypt_msgs_variant", "aes_tune_set", "aes_tune_get", "aes_size_bucket", "aes_batch_plan",
             "aes_ecb_batch", "aes_ecb_batch_noalloc", "aes_batch_max_grid", "aes_device_copy", "aes_roof_probe", "aes_host_tables", "aes_server_workspace_bytes",
             "aes_server_staging_bytes", "aes_server_create", "aes_server_submit", "aes_server_poll",
             "aes_server_release", "aes_server_stats", "aes_server_destroy", "aes_serve_replay", "aes_pipe_create",
@@ -318,6 +323,21 @@ def aes_cbc_encrypt_msgs(rk, nr: int, msgs_dev, nmsgs: int, in_base, out_base, r
     and ``out_base``; rk is the encryption schedule.  ``rejected_dev`` (a
     device int32/uint32 tensor, or None) receives the count of skipped
     messages."""
+    lib = _lib()
+    return _cbc_msgs(lib.aes_cbc_encrypt_msgs, lib.aes_cbc_encrypt_msgs_variant, rk, nr, msgs_dev, nmsgs, in_base,
+                     out_base, rejected_dev, variant, stream)
+
+
+def aes_cbc_decrypt_msgs(rk, nr: int, msgs_dev, nmsgs: int, in_base, out_base, rejected_dev=None,
+                         variant: Variant | None = None, stream=None):
+    """CBC decryption of a message set (as aes_cbc_encrypt_msgs); rk is the
+    decryption schedule."""
+    lib = _lib()
+    return _cbc_msgs(lib.aes_cbc_decrypt_msgs, lib.aes_cbc_decrypt_msgs_variant, rk, nr, msgs_dev, nmsgs, in_base,
+                     out_base, rejected_dev, variant, stream)
+
+
+def _cbc_msgs(fn, fn_variant, rk, nr, msgs_dev, nmsgs, in_base, out_base, rejected_dev, variant, stream):
     nmsgs = int(nmsgs)
     if nmsgs < 0 or _bytes_of(msgs_dev, "msgs_dev") < nmsgs * CBC_MSG_DTYPE.itemsize:
         raise ValueError("message tensor smaller than nmsgs records")
@@ -330,10 +350,10 @@ def aes_cbc_encrypt_msgs(rk, nr: int, msgs_dev, nmsgs: int, in_base, out_base, r
     args = [rk.ctypes.data_as(_u32p), int(nr), msgs_dev.data_ptr(), nmsgs, in_base.data_ptr(),
             _blocks_of(in_base, "in_base"), out_base.data_ptr(), _blocks_of(out_base, "out_base"), rej]
     if variant is None:
-        _check(_lib().aes_cbc_encrypt_msgs(*args, _stream_handle(stream)))
+        _check(fn(*args, _stream_handle(stream)))
     else:
         v = variant._c()
-        _check(_lib().aes_cbc_encrypt_msgs_variant(*args, ctypes.byref(v), _stream_handle(stream)))
+        _check(fn_variant(*args, ctypes.byref(v), _stream_handle(stream)))
     return out_base
 
 

@@ -292,10 +292,26 @@ aes_variant cbc_msgs_default(size_t nmsgs, int cus)
     return aes_variant{quads ? AES_BPT_COLUMN : 8, wg, AES_PLACEMENT_TTABLE4, 0};
 }
 
-// v == nullptr: the default shape for this many messages (cbc_msgs_default).
-int run_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs, const void* in_base,
-                         size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev,
-                         const aes_variant* v, void* stream)
+// Shape of aes_cbc_decrypt_msgs when the caller names none, on 4 tables: one
+// wave per message (2 blocks per lane per unit) when the input arena averages
+// at least 64 blocks per message, so that a wave's lanes all have blocks,
+// else one message per lane with 4 independent blocks at a time; workgroups
+// just large enough to give every CU the same number of waves, up to 1024.
+aes_variant cbc_dec_msgs_default(size_t nmsgs, size_t in_blocks, int cus)
+{
+    const uint64_t c = cus > 0 ? (uint64_t)cus : 256u;
+    const bool wave = nmsgs > 0 && in_blocks / nmsgs >= 64u;
+    const uint64_t waves = wave ? nmsgs : (nmsgs + 63u) / 64u;
+    const uint64_t per_cu = (waves + c - 1) / c;
+    const int wg = (int)std::min<uint64_t>(1024u, 64u * std::max<uint64_t>(per_cu, 1u));
+    return aes_variant{wave ? AES_BPT_WAVE_MSG + 2 : 4, wg, AES_PLACEMENT_TTABLE4, 0};
+}
+
+// Encryption (decrypt == false) or decryption of a CBC message set; v ==
+// nullptr: the default shape for this many messages.
+int run_cbc_msgs(bool decrypt, const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs,
+                 const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev,
+                 const aes_variant* v, void* stream)
 {
     if (!valid_nr(nr))
         return fail(AES_EINVAL, "nr must be 10, 12 or 14, got %d", nr);
@@ -319,7 +335,11 @@ int run_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev
     if (ib != ob && ib < ob + (uint64_t)out_blocks * 16u && ob < ib + (uint64_t)in_blocks * 16u)
         return fail(AES_EINVAL, "in and out arenas overlap without being the same buffer");
     if (v != nullptr) {
-        if (v->bpt != AES_BPT_COLUMN && v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != 8)
+        if (decrypt && v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != AES_BPT_WAVE_MSG + 1 &&
+            v->bpt != AES_BPT_WAVE_MSG + 2)
+            return fail(AES_EINVAL, "bpt must be 1, 2 or 4 (one message per lane) or AES_BPT_WAVE_MSG + 1 or 2 "
+                                    "(one wave per message), got %d", v->bpt);
+        if (!decrypt && v->bpt != AES_BPT_COLUMN && v->bpt != 1 && v->bpt != 2 && v->bpt != 4 && v->bpt != 8)
             return fail(AES_EINVAL,
                         "bpt (blocks a lane loads at once) must be 1, 2, 4 or 8, or AES_BPT_COLUMN, got %d", v->bpt);
         aes_variant shape_only = *v;
@@ -328,20 +348,24 @@ int run_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev
         if (rc != AES_OK)
             return rc;
         if (v->placement == AES_PLACEMENT_BITSLICED)
-            return fail(AES_EINVAL, "CBC encryption runs on the table placements only (not bitsliced)");
+            return fail(AES_EINVAL, "CBC message sets run on the table placements only (not bitsliced)");
     }
     RoundKeys keys{};
     std::memcpy(keys.w, rk, sizeof(uint32_t) * 4 * (nr + 1));
     int cus = device_cu_count();
     if (cus <= 0)
         return fail(AES_EHIP, "cannot query the current HIP device");
-    const aes_variant chosen = v != nullptr ? *v : cbc_msgs_default(nmsgs, cus);
+    const aes_variant chosen =
+        v != nullptr ? *v : decrypt ? cbc_dec_msgs_default(nmsgs, in_blocks, cus) : cbc_msgs_default(nmsgs, cus);
     v = &chosen;
     LaunchShape shape{v->bpt, v->wg, v->grid};
-    hipError_t e = launch_cbc_encrypt_msgs(shape, v->placement, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base,
-                                           out_blocks, rejected_dev, keys, cus, static_cast<hipStream_t>(stream));
+    hipError_t e =
+        decrypt ? launch_cbc_decrypt_msgs(shape, v->placement, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base,
+                                          out_blocks, rejected_dev, keys, cus, static_cast<hipStream_t>(stream))
+                : launch_cbc_encrypt_msgs(shape, v->placement, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base,
+                                          out_blocks, rejected_dev, keys, cus, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
-        return fail_hip(e, "CBC encryption kernel launch");
+        return fail_hip(e, decrypt ? "CBC decryption kernel launch" : "CBC encryption kernel launch");
     return AES_OK;
 }
 
@@ -567,8 +591,8 @@ int aes_cbc_decrypt_variant(const uint32_t* rk, int nr, const uint8_t* iv, const
 int aes_cbc_encrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs, const void* in_base,
                          size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev, void* stream)
 {
-    return run_cbc_encrypt_msgs(rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
-                                nullptr, stream);
+    return run_cbc_msgs(false, rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                        nullptr, stream);
 }
 
 int aes_cbc_encrypt_msgs_variant(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs,
@@ -577,8 +601,25 @@ int aes_cbc_encrypt_msgs_variant(const uint32_t* rk, int nr, const aes_cbc_msg* 
 {
     if (variant == nullptr)
         return fail(AES_EINVAL, "null variant");
-    return run_cbc_encrypt_msgs(rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
-                                variant, stream);
+    return run_cbc_msgs(false, rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                        variant, stream);
+}
+
+int aes_cbc_decrypt_msgs(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs, const void* in_base,
+                         size_t in_blocks, void* out_base, size_t out_blocks, uint32_t* rejected_dev, void* stream)
+{
+    return run_cbc_msgs(true, rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                        nullptr, stream);
+}
+
+int aes_cbc_decrypt_msgs_variant(const uint32_t* rk, int nr, const aes_cbc_msg* msgs_dev, size_t nmsgs,
+                                 const void* in_base, size_t in_blocks, void* out_base, size_t out_blocks,
+                                 uint32_t* rejected_dev, const aes_variant* variant, void* stream)
+{
+    if (variant == nullptr)
+        return fail(AES_EINVAL, "null variant");
+    return run_cbc_msgs(true, rk, nr, msgs_dev, nmsgs, in_base, in_blocks, out_base, out_blocks, rejected_dev,
+                        variant, stream);
 }
 
 int aes_tune_set(int nr, int decrypt, size_t nblocks, const aes_variant* v)

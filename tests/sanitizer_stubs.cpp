@@ -46,6 +46,12 @@ hipError_t launch_cbc_encrypt_msgs(const LaunchShape&, int, int, const void*, ui
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_cbc_decrypt_msgs(const LaunchShape&, int, int, const void*, uint64_t, const void*, uint64_t, void*,
+                                   uint64_t, uint32_t*, const RoundKeys&, int, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_host_word(uint32_t*, uint32_t, hipStream_t) { return hipErrorInvalidValue; }
 
 hipError_t launch_batch(const BatchArgs&, int, int, int, int, hipStream_t) { return hipErrorInvalidValue; }

@@ -6,7 +6,9 @@ group, gaps and a shuffled output order) for every key size, every kernel
 variant with a small grid so waves take several wave units, both kernels
 on every table placement for 192- and 256-bit keys, in-place messages, a
 message continued across two launches, messages the kernel must skip, and
-the 1 GiB set of 2^18 four-KiB messages on sampled messages."""
+the 1 GiB set of 2^18 four-KiB messages on sampled messages; and the same
+for CBC decryption of message sets against the oracle's CBC decryption
+(every variant, in place with skipped records, 2^18 x 4 KiB on samples)."""
 import numpy as np
 import pytest
 
@@ -195,6 +197,131 @@ def test_empty_list_is_a_no_op():
     msgs = torch.zeros(48, dtype=torch.uint8, device="cuda")
     aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, 0, torch.zeros(64, dtype=torch.uint8, device="cuda"), out)
     assert (to_host(out) == SENTINEL).all()
+
+
+# ------------------------------------------------------------ decryption
+def run_dec(ks, recs, src_dev, out_dev, variant=None, rejected=None):
+    torch = cuda()
+    msgs = to_dev(recs.view(np.uint8))
+    aes.aes_cbc_decrypt_msgs(ks.rk_dec, ks.nr, msgs, recs.size, src_dev, out_dev, rejected_dev=rejected,
+                             variant=variant)
+    torch.cuda.synchronize()
+
+
+def check_decrypted(oracle_lib, key, recs, src: np.ndarray, got: np.ndarray, what: str, idx=None):
+    for m in (range(recs.size) if idx is None else idx):
+        r = recs[m]
+        a, n, o = int(r["in_block"]) * 16, int(r["nblocks"]) * 16, int(r["out_block"]) * 16
+        want = oracle_lib.cbc_decrypt(key, r["iv"].tobytes(), src[a:a + n]) if n else np.zeros(0, np.uint8)
+        i = first_mismatch(got[o:o + n], want)
+        assert i is None, "%s: message %d (%d blocks) first differing byte %d" % (what, m, n // 16, i)
+
+
+@pytest.mark.parametrize("keybits", [128, 192, 256])
+def test_decrypt_ragged_message_set_matches_oracle(oracle_lib, keybits):
+    # random bytes as ciphertext: the oracle's CBC decryption of each message
+    torch = cuda()
+    ms = inputs.cbc_message_set(890 + keybits, 1500, 200)
+    key = inputs.random_key(891, keybits)
+    ks = aes.aes_expand_key(key)
+    src = inputs.random_bytes(892 + keybits, 16 * ms.in_blocks)
+    out = torch.full((16 * ms.out_blocks,), SENTINEL, dtype=torch.uint8, device="cuda")
+    recs = records(ms)
+    rej = torch.zeros(1, dtype=torch.int32, device="cuda")
+    run_dec(ks, recs, to_dev(src), out, rejected=rej)
+    got = to_host(out)
+    assert int(rej.item()) == 0
+    check_decrypted(oracle_lib, key, recs, src, got, "%d-bit" % keybits)
+    untouched_outside(recs, got, "%d-bit" % keybits)
+
+
+DEC_VARIANTS = [aes.Variant(bpt=b, wg=w, placement=p, grid=3) for p in (0, 1, 2)
+                for b in (1, 2, 4, aes.AES_BPT_WAVE_MSG + 1, aes.AES_BPT_WAVE_MSG + 2) for w in (64, 1024)]
+
+
+@pytest.mark.parametrize("variant", DEC_VARIANTS, ids=lambda v: "p%d_g%d_w%d" % (v.placement, v.bpt, v.wg))
+def test_decrypt_every_variant_matches_oracle(oracle_lib, variant):
+    torch = cuda()
+    ms = inputs.cbc_message_set(893, 700, 37)
+    key = inputs.random_key(894, 256)
+    ks = aes.aes_expand_key(key)
+    src = inputs.random_bytes(895, 16 * ms.in_blocks)
+    out = torch.full((16 * ms.out_blocks,), SENTINEL, dtype=torch.uint8, device="cuda")
+    recs = records(ms)
+    run_dec(ks, recs, to_dev(src), out, variant=variant)
+    got = to_host(out)
+    check_decrypted(oracle_lib, key, recs, src, got, str(variant))
+    untouched_outside(recs, got, str(variant))
+
+
+@pytest.mark.parametrize("keybits", [128, 256])
+def test_decrypt_long_messages_one_wave_each(oracle_lib, keybits):
+    # messages averaging well over 64 blocks: the default takes one wave per
+    # message; lengths straddle the 64- and 128-block units, plus empty ones
+    torch = cuda()
+    ms = inputs.cbc_message_set(905 + keybits, 300, 700)
+    key = inputs.random_key(906, keybits)
+    ks = aes.aes_expand_key(key)
+    src = inputs.random_bytes(907 + keybits, 16 * ms.in_blocks)
+    out = torch.full((16 * ms.out_blocks,), SENTINEL, dtype=torch.uint8, device="cuda")
+    recs = records(ms)
+    # shorten six long messages to the unit boundaries (ranges stay disjoint)
+    longs = np.nonzero(recs["nblocks"] >= 129)[0][:6]
+    recs["nblocks"][longs] = [63, 64, 65, 127, 128, 129]
+    assert ms.in_blocks // recs.size >= 64
+    run_dec(ks, recs, to_dev(src), out)
+    got = to_host(out)
+    check_decrypted(oracle_lib, key, recs, src, got, "%d-bit long" % keybits)
+    untouched_outside(recs, got, "%d-bit long" % keybits)
+    buf = to_dev(src)                                      # in place, one wave per message
+    inplace = recs.copy()
+    inplace["out_block"] = inplace["in_block"]
+    run_dec(ks, inplace, buf, buf, variant=aes.Variant(bpt=aes.AES_BPT_WAVE_MSG + 2, wg=256))
+    check_decrypted(oracle_lib, key, inplace, src, to_host(buf), "%d-bit long in place" % keybits)
+
+
+def test_decrypt_round_trip_in_place_and_skips(oracle_lib):
+    # encrypt a ragged set with the GPU, decrypt it in place, and skip bad records
+    torch = cuda()
+    ms = inputs.cbc_message_set(896, 900, 60)
+    key = inputs.random_key(897, 192)
+    ks = aes.aes_expand_key(key)
+    plain = inputs.random_bytes(898, 16 * ms.in_blocks)
+    recs = records(ms)
+    recs["out_block"] = recs["in_block"]
+    buf = to_dev(plain)
+    run(ks, recs, buf, buf)                               # in-place encryption
+    cipher = to_host(buf)
+    check_messages(oracle_lib, key, recs, plain, cipher, "encrypt in place")
+    bad = recs.copy()
+    bad["in_block"][7] = ms.in_blocks
+    bad["reserved"][11] = 5
+    rej = torch.zeros(1, dtype=torch.int32, device="cuda")
+    run_dec(ks, bad, buf, buf, rejected=rej)              # in-place decryption
+    assert int(rej.item()) == 2
+    got = to_host(buf)
+    for m in range(recs.size):
+        a, n = int(recs[m]["in_block"]) * 16, int(recs[m]["nblocks"]) * 16
+        want = cipher[a:a + n] if m in (7, 11) else plain[a:a + n]
+        assert first_mismatch(got[a:a + n], want) is None, m
+
+
+def test_decrypt_one_gib_of_four_kib_messages_on_samples(oracle_lib):
+    torch = cuda()
+    n, blocks = 1 << 18, 256
+    ms = inputs.cbc_equal_messages(899, n, blocks)
+    key = inputs.random_key(899, 128)
+    ks = aes.aes_expand_key(key)
+    src = inputs.device_random_bytes(899, 16 * ms.in_blocks)
+    out = torch.empty_like(src)
+    recs = records(ms)
+    run_dec(ks, recs, src, out)
+    pick = np.unique(np.concatenate([[0, n - 1], inputs.rng(899).integers(0, n, size=64)]))
+    for m in pick:
+        a = int(m) * blocks * 16
+        s = to_host(src[a:a + blocks * 16])
+        want = oracle_lib.cbc_decrypt(key, recs[m]["iv"].tobytes(), s)
+        assert first_mismatch(to_host(out[a:a + blocks * 16]), want) is None, int(m)
 
 
 def test_one_gib_of_four_kib_messages_on_samples(oracle_lib):

@@ -294,6 +294,26 @@ def test_cbc_encrypt_msgs_argument_checks_before_any_device_call():
     assert encv(rk, 10, M, 4, A, 64, B, 64, None, None, None) == aes.AES_EINVAL  # null variant
 
 
+def test_cbc_decrypt_msgs_argument_checks_before_any_device_call():
+    lib = aes._lib()
+    rk = np.zeros(60, dtype=np.uint32).ctypes.data_as(aes._u32p)
+    M, A, B = 0x30000, 0x10000, 0x20000  # never dereferenced: every case fails in host checks
+    dec = lib.aes_cbc_decrypt_msgs
+    assert dec(rk, 9, M, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert dec(None, 10, M, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert dec(rk, 10, M, 0, A, 64, B, 64, None, None) == aes.AES_OK            # no messages: no launch
+    assert dec(rk, 10, None, 4, A, 64, B, 64, None, None) == aes.AES_EINVAL
+    assert dec(rk, 10, M + 8, 4, A, 64, B, 64, None, None) == aes.AES_EALIGN
+    assert dec(rk, 10, M, 4, A, 64, B, 64, 0x40001, None) == aes.AES_EALIGN
+    assert dec(rk, 10, M, 4, A, 4096, A + 16, 1, None, None) == aes.AES_EINVAL   # arenas overlap
+    decv = lib.aes_cbc_decrypt_msgs_variant
+    for v in (dict(bpt=8), dict(bpt=aes.AES_BPT_COLUMN), dict(bpt=3), dict(bpt=aes.AES_BPT_WAVE_MSG + 4),
+              dict(bpt=aes.AES_BPT_WAVE_MSG), dict(placement=aes.AES_PLACEMENT_BITSLICED, wg=256), dict(wg=1088)):
+        assert decv(rk, 10, M, 4, A, 64, B, 64, None, aes.ctypes.byref(aes.Variant(**v)._c()), None) == \
+            aes.AES_EINVAL, v
+    assert decv(rk, 10, M, 4, A, 64, B, 64, None, None, None) == aes.AES_EINVAL  # null variant
+
+
 def test_cbc_msg_record_layout():
     # the numpy record the binding builds is the C struct aes_cbc_msg
     assert aes.CBC_MSG_DTYPE.itemsize == 48
