@@ -877,7 +877,8 @@ def main():
                          "trace); corun-sweep: their sustained rates over bitsliced shares 0 ... 0.24; ctr: 1 GiB CTR and ECB "
                          "encryptions in turn (for counters); cbc-msgs: 3 copies of 1 GiB, then CBC encryption of 1 GiB as "
                          "2^18 messages of 4 KiB and ECB encryption of the same buffer, in turn, then CBC encryption "
-                         "of 1 GiB as 2^16 messages of 16 KiB (for counters and traces); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
+                         "of 1 GiB as 2^16 messages of 16 KiB, then CBC decryption of the 4 KiB set (for counters and "
+                         "traces); variants: the tuned defaults at 256 KiB, 4 and 16 MiB "
                          "and the bitsliced kernel at 1 GiB (for counters); host: the host-inclusive file-size sweep "
                          "only (for a kernel and copy trace)")
     args = ap.parse_args()
@@ -955,6 +956,8 @@ def main():
             aes.aes_ecb_encrypt(ks.rk_enc, ks.nr, x, y)
         for _ in range(max(1, args.steps)):
             aes.aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs_q, nq, x, y)
+        for _ in range(max(1, args.steps)):  # decryption of the 4 KiB set: one wave per message
+            aes.aes_cbc_decrypt_msgs(ks.rk_dec, ks.nr, msgs, nm, x, y)
         torch.cuda.synchronize()
         log("cbc-msgs profile launches done")
         return
