@@ -407,6 +407,32 @@ def cbc_decrypt(ks: KeySchedule, iv: bytes, x, out=None, stream=None):
     return aes_cbc_decrypt(ks.rk_dec, ks.nr, iv, x, out, stream=stream)
 
 
+def _msgs_on_device(recs, like):
+    import torch
+    if isinstance(recs, torch.Tensor):
+        return recs, (recs.numel() * recs.element_size()) // CBC_MSG_DTYPE.itemsize
+    recs = np.ascontiguousarray(recs, dtype=CBC_MSG_DTYPE)
+    return torch.from_numpy(recs.view(np.uint8)).to(like.device), recs.size
+
+
+def cbc_encrypt_msgs(ks: KeySchedule, recs, x, out=None, stream=None):
+    """CBC encryption of the message set ``recs`` (a host numpy array of
+    CBC_MSG_DTYPE records, or a device uint8 tensor holding them) from the
+    uint8 CUDA tensor ``x`` into ``out`` (a new tensor like ``x`` if None)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    msgs, n = _msgs_on_device(recs, x)
+    return aes_cbc_encrypt_msgs(ks.rk_enc, ks.nr, msgs, n, x, out, stream=stream)
+
+
+def cbc_decrypt_msgs(ks: KeySchedule, recs, x, out=None, stream=None):
+    """CBC decryption of the message set ``recs`` (as cbc_encrypt_msgs)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    msgs, n = _msgs_on_device(recs, x)
+    return aes_cbc_decrypt_msgs(ks.rk_dec, ks.nr, msgs, n, x, out, stream=stream)
+
+
 # ---------------------------------------------------------------- batched ECB
 def aes_batch_plan(msgs: np.ndarray, chunk_blocks: int):
     """Host planner: returns (items [ITEM_DTYPE], n_enc, n_dec)."""

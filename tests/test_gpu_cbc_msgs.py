@@ -324,6 +324,25 @@ def test_decrypt_one_gib_of_four_kib_messages_on_samples(oracle_lib):
         assert first_mismatch(to_host(out[a:a + blocks * 16]), want) is None, int(m)
 
 
+def test_helpers_take_host_records(oracle_lib):
+    # cbc_encrypt_msgs / cbc_decrypt_msgs upload a host record array themselves
+    cuda()
+    ms = inputs.cbc_message_set(910, 400, 90)
+    key = inputs.random_key(911, 128)
+    ks = aes.expand_key(key)
+    src = inputs.random_bytes(912, 16 * max(ms.in_blocks, ms.out_blocks))
+    recs = records(ms)
+    recs["out_block"] = recs["in_block"]
+    x = to_dev(src)
+    c = aes.cbc_encrypt_msgs(ks, recs, x)
+    cipher = to_host(c)
+    check_messages(oracle_lib, key, recs, src, cipher, "helper encrypt")
+    back = to_host(aes.cbc_decrypt_msgs(ks, recs, c))
+    for m in range(recs.size):
+        a, n = int(recs[m]["in_block"]) * 16, int(recs[m]["nblocks"]) * 16
+        assert first_mismatch(back[a:a + n], src[a:a + n]) is None, m
+
+
 def test_one_gib_of_four_kib_messages_on_samples(oracle_lib):
     """The benchmark's set: 2^18 messages of 256 blocks, back to back, in the
     default launch; 64 random messages plus the first and last are compared
